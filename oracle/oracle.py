@@ -1,0 +1,360 @@
+"""Plain FP64 CPU reference (the oracle) for the TPB sigma build and solver.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the CPU
+baseline leg of the benchmark may import this module.  It shares no code
+with the HIP library: the heavy loops live in ``tbsci_oracle.c`` (compiled
+here with gcc), the rest is numpy.
+
+Contents, each following the paper (arXiv 2503.10335):
+
+* ``string_index`` -- sorted keys plus caller positions; membership by a
+  Python dict (Sec. II.C: membership of a candidate string in the selected
+  set, by hashing or by sorted binary search).
+* ``lists`` -- same-spin single and double excitation lists between selected
+  strings, built by pair scan and explicit operator application
+  (Sec. II.C: the single- and double-excitation link tables of the selected
+  beta strings; Sec. III.C: one entry = target index, two orbital indices and
+  a sign).
+* ``same_spin_matrix`` -- the same-spin Hamiltonian between selected strings,
+  each element a generic Slater-Condon element of a single-spin determinant
+  (Sec. II.C, categories [2,0]/[0,2] and the one-spin parts of [1,0]/[0,1]).
+* ``sigma`` / ``diag`` / ``dense_h`` -- sigma = P H P C over the TPB space
+  (Sec. II.A, Eq. TPB_Det and the beta-fastest index map; Sec. II.C,
+  Slater-Condon rule and Algorithm 1's six categories).
+* ``davidson`` -- a plain Davidson eigensolver with collapse restart
+  (Sec. II.B, Davidson matrix-vector products; Sec. III.C, restart with a
+  bounded number of stored vectors).
+* ``fock_hamiltonian`` -- brute-force Jordan-Wigner Fock-space Hamiltonian
+  for tiny M, from the second-quantised operator, used only to pin the above.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tbsci_oracle.c")
+_LIB = os.path.join(_HERE, "libtbsci_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            i64 = ctypes.c_int64
+            lib.orc_space_new.restype = P
+            lib.orc_space_new.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, i64, P,
+                                          i64, ctypes.POINTER(ctypes.c_int)]
+            lib.orc_space_free.argtypes = [P]
+            lib.orc_sigma.argtypes = [P, P, P, P, P, P, i64, ctypes.c_int]
+            lib.orc_element.restype = ctypes.c_double
+            lib.orc_element.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint64]
+            lib.orc_dense.argtypes = [P, P, P, P, ctypes.c_int]
+            lib.orc_diag.argtypes = [P, P, P, P, P, i64, ctypes.c_int]
+            lib.orc_lists.restype = i64
+            lib.orc_lists.argtypes = [P, i64, ctypes.c_int, ctypes.c_int, P, i64, P, P, ctypes.c_int]
+            lib.orc_count_singles.restype = i64
+            lib.orc_count_singles.argtypes = [P, i64, ctypes.c_int, ctypes.c_int]
+            _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+class Space:
+    """Hash-indexed TPB space with integrals; owns contiguous copies."""
+
+    def __init__(self, M, n_alpha, n_beta, h, eri, alpha, beta):
+        lib = _load()
+        self.M, self.na, self.nb = int(M), int(n_alpha), int(n_beta)
+        self.h = np.ascontiguousarray(h, dtype=np.float64)
+        self.eri = np.ascontiguousarray(eri, dtype=np.float64)
+        self.alpha = np.ascontiguousarray(alpha, dtype=np.uint64)
+        self.beta = np.ascontiguousarray(beta, dtype=np.uint64)
+        st = ctypes.c_int(0)
+        self._p = lib.orc_space_new(self.M, self.na, self.nb, _ptr(self.h), _ptr(self.eri),
+                                    _ptr(self.alpha), len(self.alpha), _ptr(self.beta),
+                                    len(self.beta), ctypes.byref(st))
+        if st.value != 0:
+            lib.orc_space_free(self._p)
+            self._p = None
+            raise ValueError("duplicate strings in a selected list")
+        self.la, self.lb = len(self.alpha), len(self.beta)
+
+    @classmethod
+    def of(cls, prob):
+        return cls(prob.M, prob.n_alpha, prob.n_beta, prob.h, prob.eri, prob.alpha, prob.beta)
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            _load().orc_space_free(self._p)
+            self._p = None
+
+    @property
+    def n_det(self):
+        return self.la * self.lb
+
+    def sigma(self, C, rows=None, nthreads=0):
+        """sigma = P H P C; C is [la][lb] (or flat); rows selects output alpha rows."""
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(self.la, self.lb))
+        if rows is None:
+            out = np.empty((self.la, self.lb))
+            _load().orc_sigma(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(C), _ptr(out),
+                              None, 0, nthreads)
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int64)
+            out = np.empty((len(rows), self.lb))
+            _load().orc_sigma(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(C), _ptr(out),
+                              _ptr(rows), len(rows), nthreads)
+        return out
+
+    def diag(self, rows=None, nthreads=0):
+        if rows is None:
+            out = np.empty((self.la, self.lb))
+            _load().orc_diag(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(out), None, 0,
+                             nthreads)
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int64)
+            out = np.empty((len(rows), self.lb))
+            _load().orc_diag(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(out), _ptr(rows),
+                             len(rows), nthreads)
+        return out
+
+    def element(self, Ia, Ib, Ja, Jb):
+        return _load().orc_element(self._p, int(Ia), int(Ib), int(Ja), int(Jb))
+
+    def dense_h(self, nthreads=0):
+        n = self.n_det
+        if n > 6000:
+            raise ValueError("dense H only for small spaces")
+        H = np.empty((n, n))
+        _load().orc_dense(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(H), nthreads)
+        return H
+
+    def same_spin_matrix(self, spin):
+        """Dense same-spin Hamiltonian A_spin between selected strings.
+
+        Element (I, J) is <I|H|J> for a determinant holding electrons of one
+        spin only (the other spin string empty), i.e. the one-spin part of H.
+        """
+        strs = self.alpha if spin == 0 else self.beta
+        n = len(strs)
+        A = np.zeros((n, n))
+        for i in range(n):
+            for j in range(n):
+                if bin(int(strs[i]) ^ int(strs[j])).count("1") > 4:
+                    continue
+                if spin == 0:
+                    A[i, j] = self.element(strs[i], 0, strs[j], 0)
+                else:
+                    A[i, j] = self.element(0, strs[i], 0, strs[j])
+        return A
+
+
+# ------------------------------------------------------------------ indices
+
+def string_index(strings):
+    """(keys ascending uint64, pos int32 caller index of each sorted key)."""
+    s = np.asarray(strings, dtype=np.uint64)
+    order = sorted(range(len(s)), key=lambda i: int(s[i]))
+    return s[order].copy(), np.array(order, dtype=np.int32)
+
+
+def lookup(strings, queries):
+    """Caller index of each query string, or -1 (dict membership)."""
+    d = {int(v): i for i, v in enumerate(np.asarray(strings, dtype=np.uint64))}
+    return np.array([d.get(int(q), -1) for q in np.asarray(queries, dtype=np.uint64)],
+                    dtype=np.int32)
+
+
+def lists(strings, M, kind, rows=None, count_only=False):
+    """Canonical same-spin excitation lists by pair scan.
+
+    kind 1 (singles): per row I, entries (j, p, q, sign), I = a+_p a_q J,
+    ordered by (p, q).  kind 2 (doubles): entries (j, i, jj, a, b, sign),
+    I = a+_i a+_jj a_b a_a J, ordered by (i, jj, a, b).
+    Returns (row_ptr int64[n+1], entries int32[total, 6]) or total if count_only.
+    """
+    lib = _load()
+    s = np.ascontiguousarray(strings, dtype=np.uint64)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = len(s) if r is None else len(r)
+    ptr = np.zeros(nr + 1, dtype=np.int64)
+    tot = lib.orc_lists(_ptr(s), len(s), int(M), int(kind), _ptr(r), 0 if r is None else len(r),
+                        _ptr(ptr), None, 1)
+    if count_only:
+        return tot
+    ent = np.zeros((max(tot, 1), 6), dtype=np.int32)
+    lib.orc_lists(_ptr(s), len(s), int(M), int(kind), _ptr(r), 0 if r is None else len(r),
+                  _ptr(ptr), _ptr(ent), 0)
+    return ptr, ent[:tot]
+
+
+def singles_with_diag(strings, M, rows=None):
+    """Singles lists with the occupation entries (p = q, p in I, j = I, sign
+    +1) merged in, ordered by (p, q): the full set of E_pq links per row."""
+    ptr, ent = lists(strings, M, 1, rows)
+    s = np.asarray(strings, dtype=np.uint64)
+    idx = range(len(s)) if rows is None else rows
+    out_ptr = [0]
+    out = []
+    for r, ii in enumerate(idx):
+        I = int(s[ii])
+        row = [tuple(e) for e in ent[ptr[r]:ptr[r + 1]]]
+        row += [(int(ii), p, p, 0, 0, 1) for p in range(M) if (I >> p) & 1]
+        row.sort(key=lambda e: (e[1], e[2]))
+        out.extend(row)
+        out_ptr.append(len(out))
+    return np.array(out_ptr, dtype=np.int64), np.array(out, dtype=np.int32).reshape(-1, 6)
+
+
+def count_singles(strings, M, nthreads=0):
+    """Number of single-excitation links inside a string set (hash membership)."""
+    s = np.ascontiguousarray(strings, dtype=np.uint64)
+    return int(_load().orc_count_singles(_ptr(s), len(s), int(M), nthreads))
+
+
+# ------------------------------------------------------------------ solvers
+
+def lowest_eigpair_dense(H):
+    w, v = np.linalg.eigh(H)
+    x = v[:, 0].copy()
+    k = int(np.argmax(np.abs(x)))
+    if x[k] < 0:
+        x = -x
+    return float(w[0]), x
+
+
+def davidson(apply_h, diag, tol=1e-8, n_max=8, max_iter=500, guess=None, floor=1e-8):
+    """Plain Davidson for the lowest eigenpair of a real symmetric operator.
+
+    Guess: unit vector on the smallest diagonal element (first on ties).
+    Preconditioner t = r / (theta - H_KK), denominators below ``floor`` in
+    magnitude replaced by +-floor keeping the sign.  Gram-Schmidt twice;
+    a correction with norm < 1e-10 after orthogonalisation stops the solve.
+    Restart: when the basis reaches n_max vectors it collapses to the Ritz
+    vector.  Returns dict(energy, x, resid, iters, converged).
+    """
+    diag = np.asarray(diag, dtype=np.float64).ravel()
+    n = diag.size
+    if guess is None:
+        x0 = np.zeros(n)
+        x0[int(np.argmin(diag))] = 1.0
+    else:
+        x0 = np.asarray(guess, dtype=np.float64).ravel().copy()
+        x0 /= np.linalg.norm(x0)
+    V = [x0]
+    W = [np.asarray(apply_h(x0), dtype=np.float64).ravel()]
+    theta, x, rn = None, x0, np.inf
+    for it in range(1, max_iter + 1):
+        k = len(V)
+        G = np.array([[V[i] @ W[j] for j in range(k)] for i in range(k)])
+        G = 0.5 * (G + G.T)
+        w, y = np.linalg.eigh(G)
+        theta = float(w[0])
+        yv = y[:, 0]
+        x = sum(yv[i] * V[i] for i in range(k))
+        Wx = sum(yv[i] * W[i] for i in range(k))
+        r = Wx - theta * x
+        rn = float(np.linalg.norm(r))
+        if rn <= tol:
+            return dict(energy=theta, x=_fix_sign(x), resid=rn, iters=it, converged=True)
+        if k >= n_max:
+            nx = np.linalg.norm(x)
+            V, W = [x / nx], [Wx / nx]
+        den = theta - diag
+        small = np.abs(den) < floor
+        den[small] = np.where(den[small] < 0, -floor, floor)
+        t = r / den
+        for _ in range(2):
+            for v in V:
+                t = t - (v @ t) * v
+        nt = np.linalg.norm(t)
+        if nt < 1e-10:
+            return dict(energy=theta, x=_fix_sign(x), resid=rn, iters=it, converged=False)
+        t /= nt
+        V.append(t)
+        W.append(np.asarray(apply_h(t), dtype=np.float64).ravel())
+    return dict(energy=theta, x=_fix_sign(x), resid=rn, iters=max_iter, converged=False)
+
+
+def _fix_sign(x):
+    k = int(np.argmax(np.abs(x)))
+    return -x if x[k] < 0 else x
+
+
+# ------------------------------------------------------------ brute force
+
+def fock_hamiltonian(M, h, eri):
+    """Full Fock-space H (dimension 4^M) from Jordan-Wigner operators.
+
+    Spin orbital index: alpha orbital p -> p, beta orbital p -> M+p.  The basis
+    state with occupation bits n (bit X = spin orbital X) is the product of
+    creators in ascending spin-orbital order acting on the vacuum, so
+    a+_X |n> = (-1)^{sum_{Y<X} n_Y} |n + e_X>.
+    H = sum_{pq,s} h_pq a+_ps a_qs + 1/2 sum_{pqrs,st} (pq|rs) a+_ps a+_rt a_st a_qs.
+    Returns a scipy.sparse CSR matrix.
+    """
+    import scipy.sparse as sp
+
+    K = 2 * M
+    dim = 1 << K
+    ann = []
+    for X in range(K):
+        rows, cols, vals = [], [], []
+        for n in range(dim):
+            if (n >> X) & 1:
+                sign = -1.0 if bin(n & ((1 << X) - 1)).count("1") & 1 else 1.0
+                rows.append(n ^ (1 << X))
+                cols.append(n)
+                vals.append(sign)
+        ann.append(sp.csr_matrix((vals, (rows, cols)), shape=(dim, dim)))
+    cre = [a.T.tocsr() for a in ann]
+    H = sp.csr_matrix((dim, dim))
+    so = lambda p, s: p + s * M
+    for s in range(2):
+        for p in range(M):
+            for q in range(M):
+                if h[p, q] != 0.0:
+                    H = H + h[p, q] * (cre[so(p, s)] @ ann[so(q, s)])
+    # two-body: precompute pair operators a+_ps a_qs for reuse
+    for s in range(2):
+        for t in range(2):
+            for p in range(M):
+                for q in range(M):
+                    Lp = cre[so(p, s)]
+                    for r in range(M):
+                        for u in range(M):
+                            v = eri[p, q, r, u]
+                            if v == 0.0:
+                                continue
+                            H = H + (0.5 * v) * (Lp @ cre[so(r, t)] @ ann[so(u, t)] @ ann[so(q, s)])
+    return H.tocsr()
+
+
+def fock_index(alpha_str, beta_str, M):
+    """Fock basis index of the determinant (alpha bits low, beta bits high)."""
+    return int(alpha_str) | (int(beta_str) << M)

@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs for TPB sigma builds and ground-state solves.
+
+This module only draws inputs: one-electron integrals h, two-electron
+integrals (pq|rs) in chemists' notation, and selected alpha/beta string
+lists.  It holds none of the Hamiltonian arithmetic, so both the HIP path
+and the CPU reference can be driven from the same inputs.
+
+Recipe (the paper's molecular FCIDUMP files are not available, so these
+stand in for them):
+
+* h_pp = -1 + 2p/M (p is 0-based); off-diagonal h_pq ~ N(0, 0.05), mirrored.
+* (pq|rs) = sum_{L<M} B^L_pq B^L_rs with B^L symmetric, entries ~ N(0, 0.15).
+  This gives the 8-fold permutational symmetry of real orbitals and a
+  positive semidefinite supermatrix.
+* Draw order from ``numpy.random.default_rng(seed)``: the strict upper
+  triangle of h row-major, then for L = 0..M-1 the upper triangle of B^L
+  including the diagonal, row-major.
+* String selection: every M-bit string with N set bits, enumerated in
+  ascending integer order, gets one N(0, 0.1) noise draw; the score is the
+  sum of occupied h_pp plus the noise; the ``n`` lowest scores are kept
+  (ties broken by the smaller integer).  The kept list is returned in rank
+  order, which is not sorted by integer value.
+
+Strings are uint64 with bit p set when spatial orbital p is occupied.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def integrals(M: int, seed: int):
+    """Return (h[M,M], eri[M,M,M,M]) float64 from the seeded recipe."""
+    rng = np.random.default_rng(seed)
+    h = np.zeros((M, M))
+    for p in range(M):
+        h[p, p] = -1.0 + 2.0 * p / M
+    iu = np.triu_indices(M, 1)
+    off = rng.normal(0.0, 0.05, size=len(iu[0]))
+    h[iu] = off
+    h[(iu[1], iu[0])] = off
+    iu0 = np.triu_indices(M, 0)
+    B = np.zeros((M, M, M))
+    for L in range(M):
+        v = rng.normal(0.0, 0.15, size=len(iu0[0]))
+        B[L][iu0] = v
+        B[L][(iu0[1], iu0[0])] = v
+    eri = np.einsum("lpq,lrs->pqrs", B, B, optimize=True)
+    # enforce exact 8-fold symmetry bitwise (einsum rounding can differ by 1 ulp)
+    eri = (eri + eri.transpose(1, 0, 2, 3)) * 0.5
+    eri = (eri + eri.transpose(0, 1, 3, 2)) * 0.5
+    eri = (eri + eri.transpose(2, 3, 0, 1)) * 0.5
+    return np.ascontiguousarray(h), np.ascontiguousarray(eri)
+
+
+def all_strings(M: int, N: int) -> np.ndarray:
+    """Every M-bit string with N set bits, ascending integer order."""
+    if N == 0:
+        return np.zeros(1, dtype=np.uint64)
+    out = []
+    for occ in itertools.combinations(range(M), N):
+        v = 0
+        for p in occ:
+            v |= 1 << p
+        out.append(v)
+    out.sort()
+    return np.array(out, dtype=np.uint64)
+
+
+def _occ_matrix(strings: np.ndarray, M: int) -> np.ndarray:
+    bits = np.arange(M, dtype=np.uint64)
+    return ((strings[:, None] >> bits[None, :]) & np.uint64(1)).astype(np.float64)
+
+
+def select_strings(M: int, N: int, n_keep: int, h: np.ndarray, seed: int,
+                   noise_std: float = 0.1) -> np.ndarray:
+    """Keep the n_keep lowest-scoring strings (rank order)."""
+    cand = all_strings(M, N)
+    rng = np.random.default_rng(seed)
+    noise = rng.normal(0.0, noise_std, size=len(cand))
+    score = _occ_matrix(cand, M) @ np.diag(h) + noise
+    order = np.lexsort((cand, score))  # primary: score, ties: smaller integer
+    n_keep = min(n_keep, len(cand))
+    return np.ascontiguousarray(cand[order[:n_keep]])
+
+
+@dataclass
+class Problem:
+    """One TPB eigenproblem: integrals plus selected alpha/beta strings."""
+    name: str
+    M: int
+    n_alpha: int
+    n_beta: int
+    h: np.ndarray
+    eri: np.ndarray
+    alpha: np.ndarray
+    beta: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_det(self) -> int:
+        return len(self.alpha) * len(self.beta)
+
+
+def make_problem(name: str, M: int, N: int, n_keep: int | None, int_seed: int,
+                 sel_seed: int | None = None, independent_beta: bool = False) -> Problem:
+    """Closed-shell-count problem (N_alpha = N_beta = N).
+
+    n_keep None keeps every string (FCI limit of the TPB space, strings in
+    ascending integer order).  With ``independent_beta`` the beta list is
+    drawn with its own noise (seed sel_seed + 1) instead of reusing alpha's.
+    """
+    h, eri = integrals(M, int_seed)
+    if n_keep is None or n_keep >= math.comb(M, N):
+        a = all_strings(M, N)
+        b = a.copy()
+    else:
+        a = select_strings(M, N, n_keep, h, sel_seed)
+        b = select_strings(M, N, n_keep, h, sel_seed + 1) if independent_beta else a.copy()
+    return Problem(name, M, N, N, h, eri, a, b,
+                   dict(int_seed=int_seed, sel_seed=sel_seed, n_keep=n_keep))
+
+
+# The five workloads: FCI-limit M=8; selected M=16 (3,000 x 3,000);
+# selected M=20 (20,000 x 20,000); FCI M=18 (48,620 x 48,620); serving mix.
+CONFIGS = {
+    "fci_m8": dict(M=8, N=4, n_keep=None, int_seed=1001),
+    "sel_m16": dict(M=16, N=8, n_keep=3000, int_seed=1002, sel_seed=2002),
+    "sel_m20": dict(M=20, N=10, n_keep=20000, int_seed=1003, sel_seed=2003),
+    "fci_m18": dict(M=18, N=9, n_keep=None, int_seed=1004),
+}
+
+
+def config(name: str) -> Problem:
+    c = dict(CONFIGS[name])
+    return make_problem(name, c.pop("M"), c.pop("N"), c.pop("n_keep"), **c)
+
+
+def random_selection(M: int, na: int, nb: int, la: int, lb: int, seed: int,
+                     int_seed: int | None = None) -> Problem:
+    """Uniformly random (non energy-ranked) selections, for small tests."""
+    rng = np.random.default_rng(seed)
+    h, eri = integrals(M, seed if int_seed is None else int_seed)
+    A = all_strings(M, na)
+    B = all_strings(M, nb)
+    a = A[rng.permutation(len(A))[:min(la, len(A))]]
+    b = B[rng.permutation(len(B))[:min(lb, len(B))]]
+    return Problem(f"rand_m{M}", M, na, nb, h, eri, np.ascontiguousarray(a),
+                   np.ascontiguousarray(b), dict(seed=seed))
+
+
+def random_vector(n_alpha_rows: int, n_beta_cols: int, seed: int = 7) -> np.ndarray:
+    """N(0,1) CI matrix [l_alpha][l_beta], normalised to unit 2-norm."""
+    rng = np.random.default_rng(seed)
+    C = rng.standard_normal((n_alpha_rows, n_beta_cols))
+    C /= np.linalg.norm(C)
+    return C
+
+
+def serving_mix(n_requests: int = 512, seed: int = 5005, rate_per_s: float = 10.0):
+    """Request stream: M uniform in {10,12,14,16}, N = M/2, string count
+    log-uniform in [500, 4000] clamped to C(M, N), Poisson arrival times.
+
+    Returns a list of dicts with keys M, N, n_keep, int_seed, sel_seed, t_arrive.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for i in range(n_requests):
+        M = int(rng.choice([10, 12, 14, 16]))
+        N = M // 2
+        n = int(round(math.exp(rng.uniform(math.log(500), math.log(4000)))))
+        n = min(n, math.comb(M, N))
+        t += rng.exponential(1.0 / rate_per_s)
+        out.append(dict(M=M, N=N, n_keep=n, int_seed=50000 + i, sel_seed=60000 + i,
+                        t_arrive=t))
+    return out
+
+
+def serving_problem(req: dict) -> Problem:
+    return make_problem(f"req_m{req['M']}_{req['n_keep']}", req["M"], req["N"],
+                        req["n_keep"], req["int_seed"], req["sel_seed"])

@@ -1,0 +1,208 @@
+/*
+ * tbsci.h -- C ABI of the MI355X TPB sigma library (libtbsci.so).
+ *
+ * The library builds sigma = H*C over a tensor-product-bitstring (TPB)
+ * determinant space and finds the lowest eigenpair with a Davidson solver,
+ * all on one AMD Instinct GPU (gfx950).  Reference: arXiv 2503.10335,
+ * "A Scalable Diagonalization Framework for Tensor-Product Bitstring
+ * Selected Configuration Interaction".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Orbitals p = 0..M-1 are spatial orbitals; a string is a uint64 with bit
+ *   p set when orbital p is occupied (M <= 64).
+ * - The determinant space is every product of a selected alpha string with a
+ *   selected beta string (Sec. II.A, Eq. TPB_Det).  The CI vector C and
+ *   sigma are row-major matrices [l_alpha][l_beta]: the determinant index
+ *   runs fastest over beta (Sec. II.A, the index map K = (w-1) l_beta + u,
+ *   here 0-based K = i_alpha * l_beta + i_beta), rows and columns in the
+ *   caller's list order.
+ * - H = sum_{pq,s} h_pq a+_ps a_qs + 1/2 sum_{pqrs,st} (pq|rs) a+_ps a+_rt a_st a_qs
+ *   with real integrals; (pq|rs) in chemists' notation.  Excitations that
+ *   leave the selected space are projected out: sigma = P H P C.
+ * - A determinant is the product of alpha creators (ascending orbital) and
+ *   then beta creators (ascending orbital) on the vacuum.
+ * - Every function returns an int status (TBSCI_OK = 0, TBSCI_PENDING = 1,
+ *   errors < 0) and never aborts; tbsci_last_error() gives a message
+ *   (thread-local).  On error, caller-owned outputs are left untouched.
+ * - Host pointers are read during the call only; the library deep-copies
+ *   what it keeps.  Device pointers are caller-owned allocations on the
+ *   context's device (for example torch tensors' data_ptr()).  A stream
+ *   argument is a hipStream_t owned by the caller; NULL is the default
+ *   stream.  A context is not thread-safe: one caller thread at a time.
+ */
+#ifndef TBSCI_H
+#define TBSCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TBSCI_OK 0
+#define TBSCI_PENDING 1
+#define TBSCI_E_INVAL (-1)    /* invalid argument or input data            */
+#define TBSCI_E_NOMEM (-2)    /* device or host allocation failed          */
+#define TBSCI_E_DEVICE (-3)   /* HIP runtime error                         */
+#define TBSCI_E_NOTCONV (-4)  /* Davidson hit max_iter or stagnated        */
+#define TBSCI_E_NOTFOUND (-5) /* unknown ticket                            */
+#define TBSCI_E_STATE (-6)    /* call not valid in the object's state      */
+
+/* element type of C and sigma in tbsci_sigma */
+#define TBSCI_FP64 0
+#define TBSCI_FP32 1 /* FP32 inputs, FP32 arithmetic and accumulation      */
+/* Davidson precision: FP32 sigma phase, then FP64 correction phase        */
+#define TBSCI_MIXED 2
+
+typedef struct tbsci_ctx tbsci_ctx;
+
+/*
+ * Create a context: validate the inputs, copy them to the device, build the
+ * sorted string index (Sec. II.C: membership of an excited string in the
+ * selected set by sorted list and binary search), the in-selection
+ * excitation lists of both spins (Sec. II.C: single and double excitation
+ * link tables, precomputed once and reused by every sigma), the same-spin
+ * operator values and the folded (pq|rs) block.
+ *
+ *   M         number of spatial orbitals, 1..64
+ *   n_alpha   electrons per alpha string (0..M); n_beta likewise
+ *   h         host, M*M row-major, symmetric to 1e-12 relative
+ *   eri       host, M^4 row-major, eri[((p*M+q)*M+r)*M+s] = (pq|rs), with the
+ *             8-fold symmetry of real orbitals to 1e-12 relative
+ *   alpha     host, l_alpha unique strings, each with n_alpha bits below M
+ *   beta      host, l_beta unique strings, each with n_beta bits below M
+ *   device    HIP device ordinal
+ *   out       receives the context; untouched on error
+ * Errors: TBSCI_E_INVAL for any violated condition above, l < 1,
+ * l > 2^31-1 or a NULL pointer; TBSCI_E_NOMEM / TBSCI_E_DEVICE.
+ */
+int tbsci_create(int M, int n_alpha, int n_beta, const double *h, const double *eri,
+                 const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta,
+                 int64_t l_beta, int device, tbsci_ctx **out);
+
+/* Free the context and its device memory.  NULL-safe. */
+void tbsci_destroy(tbsci_ctx *ctx);
+
+/* Sizes: l_alpha, l_beta and n_det = l_alpha * l_beta (any output may be NULL). */
+int tbsci_dims(const tbsci_ctx *ctx, int64_t *l_alpha, int64_t *l_beta, int64_t *n_det);
+
+/*
+ * sigma = P H P C (Sec. II.B: the matrix-vector product W = H U that
+ * dominates the Davidson solver; Sec. II.C and Algorithm 1: the six
+ * excitation categories [2,0] [1,1] [1,0] [0,2] [0,1] [0,0]).
+ *
+ *   C_dev, sigma_dev  device, [l_alpha][l_beta], double (TBSCI_FP64) or
+ *                     float (TBSCI_FP32); sigma is overwritten; must not alias
+ *   precision         TBSCI_FP64 or TBSCI_FP32
+ *   stream            hipStream_t or NULL; the call is asynchronous
+ */
+int tbsci_sigma(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precision, void *stream);
+
+/*
+ * Diagonal H_KK of every determinant (Sec. II.C: the [0,0] category,
+ * precomputed and stored), device double [l_alpha][l_beta], asynchronous.
+ */
+int tbsci_diag(tbsci_ctx *ctx, double *diag_dev, void *stream);
+
+typedef struct {
+    int n_max;                /* subspace size that triggers a collapse restart, 2..64 */
+    int max_iter;             /* cap on sigma builds (both phases together)            */
+    int precision;            /* TBSCI_FP64 or TBSCI_MIXED                              */
+    double tol_resid;         /* stop when the FP64 residual norm <= tol_resid          */
+    double tol_energy;        /* and |E_k - E_{k-1}| <= tol_energy (0 disables)         */
+    double fp32_switch_resid; /* mixed: leave the FP32 phase below this residual        */
+    double precond_floor;     /* smallest |theta - H_KK| in the preconditioner           */
+} tbsci_davidson_opts;
+
+typedef struct {
+    double energy;        /* lowest eigenvalue estimate (from an FP64 sigma)   */
+    double resid_norm;    /* ||H x - E x||_2 with an FP64 sigma               */
+    int iters;            /* sigma builds, both phases                         */
+    int iters_fp32;       /* sigma builds in FP32                              */
+    int iters_fp64;       /* sigma builds in FP64                              */
+    int converged;        /* 1 if the tolerances were met                       */
+    double t_total_s;     /* wall time of the solve                             */
+    double t_sigma_s;     /* part of it spent in sigma builds                   */
+} tbsci_davidson_info;
+
+/* Defaults: n_max 8, max_iter 200, FP64, tol_resid 1e-6, tol_energy 0,
+ * fp32_switch_resid 1e-4, precond_floor 1e-8. */
+void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
+
+/*
+ * Lowest eigenpair of P H P by Davidson iteration (Sec. II.B: Davidson
+ * diagonalisation built on the sigma product; Sec. III.C: restart keeps the
+ * number of stored vectors bounded).  Gram-Schmidt, the Rayleigh-Ritz
+ * projection and the residual are FP64 on the device; the k x k projected
+ * eigenproblem is solved on the host.  With TBSCI_MIXED the sigma builds
+ * run in FP32 until the residual drops below fp32_switch_resid (or stops
+ * falling), then the solver restarts from the Ritz vector with FP64 sigma
+ * builds (Sec. III.A: a matrix-vector product in single precision with
+ * everything else in double).
+ *
+ *   opts      host, NULL for defaults
+ *   guess_dev device double [l_alpha][l_beta] or NULL (unit vector on the
+ *             smallest diagonal element, first on ties)
+ *   C_out_dev device double [l_alpha][l_beta] or NULL: receives the Ritz
+ *             vector (unit norm, largest-magnitude entry positive)
+ *   info      host, required
+ * Returns TBSCI_OK, or TBSCI_E_NOTCONV with info filled when the tolerance
+ * was not met.  Synchronous with respect to the host.  Allocates its
+ * workspace ((2 n_max + 3) FP64 vectors, plus two FP32 vectors for MIXED).
+ */
+int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double *guess_dev,
+                   double *C_out_dev, tbsci_davidson_info *info, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Inspection of the create-time structures, for verification.
+ * spin: 0 = alpha, 1 = beta.
+ */
+
+/*
+ * Copy the sorted string index to host buffers of l entries each:
+ * keys ascending, pos[k] = caller index of keys[k] (Sec. II.C, sorted index
+ * list with binary search).
+ */
+int tbsci_string_index(const tbsci_ctx *ctx, int spin, uint64_t *keys_host, int32_t *pos_host);
+
+/*
+ * Binary-search n query strings in the selected list of one spin on the
+ * device: out_dev[i] = caller index of queries_dev[i], or -1.  Device
+ * buffers, asynchronous on stream.
+ */
+int tbsci_lookup(const tbsci_ctx *ctx, int spin, const uint64_t *queries_dev, int64_t n,
+                 int32_t *out_dev, void *stream);
+
+/*
+ * List kinds for tbsci_list_size / tbsci_get_list:
+ *  1  single excitations E_pq between selected strings plus the occupation
+ *     entries (p = q): row I holds (j, p, q, 0, 0, sign) with
+ *     sign = <I| a+_p a_q |J_j> != 0, ordered by (p, q);
+ *  2  double excitations: (j, i, jj, a, b, sign) with i < jj in I, a < b in
+ *     J_j, sign = <I| a+_i a+_jj a_b a_a |J_j>, ordered by (i, jj, a, b);
+ *  3  the same-spin Hamiltonian between selected strings (one-spin part of
+ *     H, Sec. II.C categories [2,0] / [0,2] and the one-spin parts of
+ *     [1,0] / [0,1] / [0,0]): CSR with the diagonal first in each row.
+ * Rows are indexed by caller index of I.
+ */
+int tbsci_list_size(const tbsci_ctx *ctx, int spin, int kind, int64_t *n_entries);
+
+/*
+ * Copy a list to the host.  row_ptr_host has l+1 entries.  For kinds 1 and
+ * 2, entries_host is int32 [n_entries][6]; for kind 3, entries_host is int32
+ * [n_entries] column indices and values_host double [n_entries] (values_host
+ * is ignored for kinds 1 and 2).
+ */
+int tbsci_get_list(const tbsci_ctx *ctx, int spin, int kind, int64_t *row_ptr_host,
+                   int32_t *entries_host, double *values_host);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *tbsci_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBSCI_H */

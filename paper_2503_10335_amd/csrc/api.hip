@@ -1,0 +1,319 @@
+// C ABI of the TPB sigma library: validation, context lifetime, sigma,
+// diagonal and inspection entry points.  Every entry point catches
+// exceptions and turns them into status codes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tbsci_internal.hpp"
+
+namespace tbsci {
+
+thread_local std::string g_err;
+
+namespace {
+
+void check_strings(const char *name, const uint64_t *s, int64_t l, int M, int n) {
+    if (!s) throw Error(TBSCI_E_INVAL, std::string(name) + " is NULL");
+    if (l < 1 || l > 2147483647LL)
+        throw Error(TBSCI_E_INVAL, std::string(name) + ": list length must be in [1, 2^31-1]");
+    for (int64_t i = 0; i < l; ++i) {
+        if (M < 64 && (s[i] >> M) != 0)
+            throw Error(TBSCI_E_INVAL, std::string(name) + ": string " + std::to_string(i) +
+                                           " has a bit at or above M");
+        if (__builtin_popcountll(s[i]) != n)
+            throw Error(TBSCI_E_INVAL, std::string(name) + ": string " + std::to_string(i) +
+                                           " has the wrong number of electrons");
+    }
+    std::vector<uint64_t> v(s, s + l);
+    std::sort(v.begin(), v.end());
+    if (std::adjacent_find(v.begin(), v.end()) != v.end())
+        throw Error(TBSCI_E_INVAL, std::string(name) + ": duplicate strings");
+}
+
+void check_integrals(int M, const double *h, const double *eri) {
+    if (!h || !eri) throw Error(TBSCI_E_INVAL, "h or eri is NULL");
+    double hmax = 0.0, gmax = 0.0;
+    const size_t M2 = (size_t)M * M, M4 = M2 * M2;
+    for (size_t i = 0; i < M2; ++i) {
+        if (!std::isfinite(h[i])) throw Error(TBSCI_E_INVAL, "h has a non-finite entry");
+        hmax = std::max(hmax, std::fabs(h[i]));
+    }
+    for (size_t i = 0; i < M4; ++i) {
+        if (!std::isfinite(eri[i])) throw Error(TBSCI_E_INVAL, "eri has a non-finite entry");
+        gmax = std::max(gmax, std::fabs(eri[i]));
+    }
+    const double th = 1e-12 * std::max(1.0, hmax), tg = 1e-12 * std::max(1.0, gmax);
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q)
+            if (std::fabs(h[p * M + q] - h[q * M + p]) > th)
+                throw Error(TBSCI_E_INVAL, "h is not symmetric");
+    auto g = [&](int p, int q, int r, int s) { return eri[(((size_t)p * M + q) * M + r) * M + s]; };
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q)
+            for (int r = 0; r < M; ++r)
+                for (int s = 0; s < M; ++s) {
+                    const double v = g(p, q, r, s);
+                    if (std::fabs(v - g(q, p, r, s)) > tg || std::fabs(v - g(p, q, s, r)) > tg ||
+                        std::fabs(v - g(r, s, p, q)) > tg)
+                        throw Error(TBSCI_E_INVAL, "eri lacks the 8-fold permutational symmetry");
+                }
+}
+
+template <typename T>
+T *dalloc(size_t n) {
+    void *p = nullptr;
+    TB_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+    return (T *)p;
+}
+
+void free_spin(Spin &s) {
+    void *ptrs[] = {s.str,  s.keys,  s.pos,   s.s_ptr,   s.s_ent, s.d_ptr, s.d_ent,
+                    s.a_ptr, s.a_col, s.a_val, s.a_val32, s.dsame, s.jocc};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    s = Spin{};
+}
+
+void destroy_ctx(Ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    for (auto &s : c->sp) free_spin(s);
+    void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete c;
+}
+
+void check_device_ptr(const void *p, int device, const char *name) {
+    if (!p) throw Error(TBSCI_E_INVAL, std::string(name) + " is NULL");
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(TBSCI_E_INVAL, std::string(name) + " is not a HIP allocation");
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        throw Error(TBSCI_E_INVAL, std::string(name) + " is not device memory");
+    if (a.device != device)
+        throw Error(TBSCI_E_INVAL, std::string(name) + " is on another device");
+}
+
+}  // namespace
+
+Ctx *ctx_of(const tbsci_ctx *p) { return (Ctx *)p; }
+
+void check_ctx(const tbsci_ctx *ctx) {
+    if (!ctx) throw Error(TBSCI_E_INVAL, "context is NULL");
+    TB_HIP(hipSetDevice(ctx_of(ctx)->device));
+}
+
+void check_dev(const void *p, int device, const char *name) { check_device_ptr(p, device, name); }
+
+}  // namespace tbsci
+
+using namespace tbsci;
+
+extern "C" {
+
+const char *tbsci_last_error(void) { return g_err.c_str(); }
+
+int tbsci_create(int M, int n_alpha, int n_beta, const double *h, const double *eri,
+                 const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta, int64_t l_beta,
+                 int device, tbsci_ctx **out) {
+    return guarded([&]() -> int {
+        if (!out) throw Error(TBSCI_E_INVAL, "out is NULL");
+        if (M < 1 || M > 64) throw Error(TBSCI_E_INVAL, "M must be in [1, 64]");
+        if (n_alpha < 0 || n_alpha > M || n_beta < 0 || n_beta > M)
+            throw Error(TBSCI_E_INVAL, "electron counts must be in [0, M]");
+        check_strings("alpha", alpha, l_alpha, M, n_alpha);
+        check_strings("beta", beta, l_beta, M, n_beta);
+        check_integrals(M, h, eri);
+        int ndev = 0;
+        TB_HIP(hipGetDeviceCount(&ndev));
+        if (device < 0 || device >= ndev) throw Error(TBSCI_E_INVAL, "no such device");
+        TB_HIP(hipSetDevice(device));
+
+        Ctx *c = new Ctx();
+        try {
+            c->M = M;
+            c->P = M * (M + 1) / 2;
+            c->device = device;
+            c->sp[0].n = n_alpha;
+            c->sp[0].l = l_alpha;
+            c->sp[1].n = n_beta;
+            c->sp[1].l = l_beta;
+            const size_t M2 = (size_t)M * M, M4 = M2 * M2, P = c->P;
+            std::vector<double> V64(P * P);
+            std::vector<float> V32(P * P);
+            for (int p = 0; p < M; ++p)
+                for (int q = 0; q <= p; ++q)
+                    for (int r = 0; r < M; ++r)
+                        for (int s = 0; s <= r; ++s) {
+                            const double v = eri[(((size_t)p * M + q) * M + r) * M + s];
+                            const size_t k = (size_t)fold_pair(p, q) * P + fold_pair(r, s);
+                            V64[k] = v;
+                            V32[k] = (float)v;
+                        }
+            hipStream_t st;
+            TB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            try {
+                c->h = dalloc<double>(M2);
+                c->eri = dalloc<double>(M4);
+                c->V64 = dalloc<double>(P * P);
+                c->V32 = dalloc<float>(P * P);
+                TB_HIP(hipMemcpyAsync(c->h, h, M2 * sizeof(double), hipMemcpyHostToDevice, st));
+                TB_HIP(hipMemcpyAsync(c->eri, eri, M4 * sizeof(double), hipMemcpyHostToDevice, st));
+                TB_HIP(hipMemcpyAsync(c->V64, V64.data(), P * P * sizeof(double),
+                                      hipMemcpyHostToDevice, st));
+                TB_HIP(hipMemcpyAsync(c->V32, V32.data(), P * P * sizeof(float),
+                                      hipMemcpyHostToDevice, st));
+                build_spin(*c, c->sp[0], alpha, st);
+                build_spin(*c, c->sp[1], beta, st);
+                TB_HIP(hipStreamSynchronize(st));
+            } catch (...) {
+                (void)hipStreamSynchronize(st);
+                (void)hipStreamDestroy(st);
+                throw;
+            }
+            TB_HIP(hipStreamDestroy(st));
+        } catch (...) {
+            destroy_ctx(c);
+            throw;
+        }
+        *out = (tbsci_ctx *)c;
+        return TBSCI_OK;
+    });
+}
+
+void tbsci_destroy(tbsci_ctx *ctx) {
+    if (!ctx) return;
+    try {
+        destroy_ctx(ctx_of(ctx));
+    } catch (...) {
+    }
+}
+
+int tbsci_dims(const tbsci_ctx *ctx, int64_t *l_alpha, int64_t *l_beta, int64_t *n_det) {
+    return guarded([&]() -> int {
+        if (!ctx) throw Error(TBSCI_E_INVAL, "context is NULL");
+        const Ctx *c = ctx_of(ctx);
+        if (l_alpha) *l_alpha = c->sp[0].l;
+        if (l_beta) *l_beta = c->sp[1].l;
+        if (n_det) *n_det = c->sp[0].l * c->sp[1].l;
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_sigma(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precision, void *stream) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        Ctx *c = ctx_of(ctx);
+        if (precision != TBSCI_FP64 && precision != TBSCI_FP32)
+            throw Error(TBSCI_E_INVAL, "precision must be TBSCI_FP64 or TBSCI_FP32");
+        check_dev(C_dev, c->device, "C");
+        check_dev(sigma_dev, c->device, "sigma");
+        if (C_dev == sigma_dev) throw Error(TBSCI_E_INVAL, "C and sigma must not alias");
+        launch_sigma(*c, C_dev, sigma_dev, precision, (hipStream_t)stream);
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_diag(tbsci_ctx *ctx, double *diag_dev, void *stream) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        Ctx *c = ctx_of(ctx);
+        check_dev(diag_dev, c->device, "diag");
+        launch_full_diag(*c, diag_dev, (hipStream_t)stream);
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_string_index(const tbsci_ctx *ctx, int spin, uint64_t *keys_host, int32_t *pos_host) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        if (spin != 0 && spin != 1) throw Error(TBSCI_E_INVAL, "spin must be 0 or 1");
+        if (!keys_host || !pos_host) throw Error(TBSCI_E_INVAL, "output is NULL");
+        const Spin &s = ctx_of(ctx)->sp[spin];
+        TB_HIP(hipMemcpy(keys_host, s.keys, s.l * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        TB_HIP(hipMemcpy(pos_host, s.pos, s.l * sizeof(int32_t), hipMemcpyDeviceToHost));
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_lookup(const tbsci_ctx *ctx, int spin, const uint64_t *queries_dev, int64_t n,
+                 int32_t *out_dev, void *stream) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        if (spin != 0 && spin != 1) throw Error(TBSCI_E_INVAL, "spin must be 0 or 1");
+        if (n < 0) throw Error(TBSCI_E_INVAL, "n < 0");
+        if (n == 0) return TBSCI_OK;
+        const Ctx *c = ctx_of(ctx);
+        check_dev(queries_dev, c->device, "queries");
+        check_dev(out_dev, c->device, "out");
+        launch_lookup(c->sp[spin], queries_dev, n, out_dev, (hipStream_t)stream);
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_list_size(const tbsci_ctx *ctx, int spin, int kind, int64_t *n_entries) {
+    return guarded([&]() -> int {
+        if (!ctx) throw Error(TBSCI_E_INVAL, "context is NULL");
+        if (spin != 0 && spin != 1) throw Error(TBSCI_E_INVAL, "spin must be 0 or 1");
+        if (!n_entries) throw Error(TBSCI_E_INVAL, "n_entries is NULL");
+        const Spin &s = ctx_of(ctx)->sp[spin];
+        if (kind == 1)
+            *n_entries = s.n_s;
+        else if (kind == 2)
+            *n_entries = s.n_d;
+        else if (kind == 3)
+            *n_entries = s.n_a;
+        else
+            throw Error(TBSCI_E_INVAL, "kind must be 1, 2 or 3");
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_get_list(const tbsci_ctx *ctx, int spin, int kind, int64_t *row_ptr_host,
+                   int32_t *entries_host, double *values_host) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        if (spin != 0 && spin != 1) throw Error(TBSCI_E_INVAL, "spin must be 0 or 1");
+        if (kind < 1 || kind > 3) throw Error(TBSCI_E_INVAL, "kind must be 1, 2 or 3");
+        if (!row_ptr_host || !entries_host || (kind == 3 && !values_host))
+            throw Error(TBSCI_E_INVAL, "output is NULL");
+        const Spin &s = ctx_of(ctx)->sp[spin];
+        const int64_t *ptr = kind == 1 ? s.s_ptr : kind == 2 ? s.d_ptr : s.a_ptr;
+        const int64_t n = kind == 1 ? s.n_s : kind == 2 ? s.n_d : s.n_a;
+        TB_HIP(hipMemcpy(row_ptr_host, ptr, (s.l + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (kind == 3) {
+            TB_HIP(hipMemcpy(entries_host, s.a_col, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+            TB_HIP(hipMemcpy(values_host, s.a_val, n * sizeof(double), hipMemcpyDeviceToHost));
+            return TBSCI_OK;
+        }
+        std::vector<Ent> e(std::max<int64_t>(n, 1));
+        TB_HIP(hipMemcpy(e.data(), kind == 1 ? s.s_ent : s.d_ent, n * sizeof(Ent),
+                         hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t *o = entries_host + 6 * i;
+            const uint32_t w = e[i].o;
+            o[0] = e[i].j;
+            if (kind == 1) {
+                o[1] = w & 63;
+                o[2] = (w >> 6) & 63;
+                o[3] = o[4] = 0;
+                o[5] = ((w >> 12) & 1) ? -1 : 1;
+            } else {
+                o[1] = w & 63;
+                o[2] = (w >> 6) & 63;
+                o[3] = (w >> 12) & 63;
+                o[4] = (w >> 18) & 63;
+                o[5] = ((w >> 24) & 1) ? -1 : 1;
+            }
+        }
+        return TBSCI_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libtbsci.so (declared in include/tbsci.h).
+
+Argument marshalling only: every step of the sigma build, the solver and
+the serving loop runs in the library's HIP kernels.  PyTorch provides the
+device memory (tensors) and the streams.  There is no CPU fallback: if the
+library is missing, loading fails with an error.
+
+Functions named tbsci_* mirror the C entry points one to one; ``Context``
+is a small convenience wrapper over them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to (same soname)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtbsci.so")
+
+TBSCI_OK = 0
+TBSCI_PENDING = 1
+TBSCI_E_INVAL = -1
+TBSCI_E_NOMEM = -2
+TBSCI_E_DEVICE = -3
+TBSCI_E_NOTCONV = -4
+TBSCI_E_NOTFOUND = -5
+TBSCI_E_STATE = -6
+TBSCI_FP64 = 0
+TBSCI_FP32 = 1
+TBSCI_MIXED = 2
+
+
+class TbsciError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tbsci error {code}: {msg}")
+        self.code = code
+
+
+class DavidsonOpts(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
+                ("tol_resid", ctypes.c_double), ("tol_energy", ctypes.c_double),
+                ("fp32_switch_resid", ctypes.c_double), ("precond_floor", ctypes.c_double)]
+
+
+class DavidsonInfo(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("resid_norm", ctypes.c_double),
+                ("iters", ctypes.c_int), ("iters_fp32", ctypes.c_int), ("iters_fp64", ctypes.c_int),
+                ("converged", ctypes.c_int), ("t_total_s", ctypes.c_double),
+                ("t_sigma_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libtbsci.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2503_10335_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, c_int, c_dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    sig = {
+        "tbsci_create": (c_int, [c_int, c_int, c_int, P, P, P, i64, P, i64, c_int, P]),
+        "tbsci_destroy": (None, [P]),
+        "tbsci_dims": (c_int, [P, P, P, P]),
+        "tbsci_sigma": (c_int, [P, P, P, c_int, P]),
+        "tbsci_diag": (c_int, [P, P, P]),
+        "tbsci_davidson_default_opts": (None, [P]),
+        "tbsci_davidson": (c_int, [P, P, P, P, P, P]),
+        "tbsci_string_index": (c_int, [P, c_int, P, P]),
+        "tbsci_lookup": (c_int, [P, c_int, P, i64, P, P]),
+        "tbsci_list_size": (c_int, [P, c_int, c_int, P]),
+        "tbsci_get_list": (c_int, [P, c_int, c_int, P, P, P]),
+        "tbsci_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().tbsci_last_error().decode()
+
+
+def _check(rc, allow=(TBSCI_OK,)):
+    if rc not in allow:
+        raise TbsciError(rc, last_error())
+    return rc
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ---------------------------------------------------------------- raw calls
+
+def tbsci_create(M, n_alpha, n_beta, h, eri, alpha, beta, device=0):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    a = np.ascontiguousarray(alpha, dtype=np.uint64)
+    b = np.ascontiguousarray(beta, dtype=np.uint64)
+    out = ctypes.c_void_p()
+    _check(load().tbsci_create(int(M), int(n_alpha), int(n_beta), _np_ptr(h), _np_ptr(eri),
+                               _np_ptr(a), len(a), _np_ptr(b), len(b), int(device),
+                               ctypes.byref(out)))
+    return out
+
+
+def tbsci_destroy(ctx):
+    load().tbsci_destroy(ctx)
+
+
+def tbsci_dims(ctx):
+    la, lb, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().tbsci_dims(ctx, ctypes.byref(la), ctypes.byref(lb), ctypes.byref(nd)))
+    return la.value, lb.value, nd.value
+
+
+def tbsci_sigma(ctx, C, S, precision=TBSCI_FP64, stream=None):
+    _check(load().tbsci_sigma(ctx, ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                              int(precision), _stream(stream)))
+
+
+def tbsci_diag(ctx, D, stream=None):
+    _check(load().tbsci_diag(ctx, ctypes.c_void_p(D.data_ptr()), _stream(stream)))
+
+
+def tbsci_davidson_default_opts():
+    o = DavidsonOpts()
+    load().tbsci_davidson_default_opts(ctypes.byref(o))
+    return o
+
+
+def tbsci_davidson(ctx, opts=None, guess=None, C_out=None, stream=None):
+    info = DavidsonInfo()
+    rc = load().tbsci_davidson(ctx, ctypes.byref(opts) if opts is not None else None,
+                               ctypes.c_void_p(guess.data_ptr()) if guess is not None else None,
+                               ctypes.c_void_p(C_out.data_ptr()) if C_out is not None else None,
+                               ctypes.byref(info), _stream(stream))
+    _check(rc, allow=(TBSCI_OK, TBSCI_E_NOTCONV))
+    return rc, info
+
+
+def tbsci_string_index(ctx, spin, l):
+    keys = np.zeros(l, dtype=np.uint64)
+    pos = np.zeros(l, dtype=np.int32)
+    _check(load().tbsci_string_index(ctx, int(spin), _np_ptr(keys), _np_ptr(pos)))
+    return keys, pos
+
+
+def tbsci_lookup(ctx, spin, queries, out, stream=None):
+    _check(load().tbsci_lookup(ctx, int(spin), ctypes.c_void_p(queries.data_ptr()), queries.numel(),
+                               ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def tbsci_list_size(ctx, spin, kind):
+    n = ctypes.c_int64()
+    _check(load().tbsci_list_size(ctx, int(spin), int(kind), ctypes.byref(n)))
+    return n.value
+
+
+def tbsci_get_list(ctx, spin, kind, l):
+    n = tbsci_list_size(ctx, spin, kind)
+    ptr = np.zeros(l + 1, dtype=np.int64)
+    if kind == 3:
+        ent = np.zeros(max(n, 1), dtype=np.int32)
+        val = np.zeros(max(n, 1), dtype=np.float64)
+        _check(load().tbsci_get_list(ctx, int(spin), 3, _np_ptr(ptr), _np_ptr(ent), _np_ptr(val)))
+        return ptr, ent[:n], val[:n]
+    ent = np.zeros((max(n, 1), 6), dtype=np.int32)
+    _check(load().tbsci_get_list(ctx, int(spin), int(kind), _np_ptr(ptr), _np_ptr(ent), None))
+    return ptr, ent[:n]
+
+
+# ---------------------------------------------------------------- wrapper
+
+class Context:
+    """One TPB problem resident on a GPU."""
+
+    def __init__(self, M, n_alpha, n_beta, h, eri, alpha, beta, device=0):
+        self.M, self.n_alpha, self.n_beta = int(M), int(n_alpha), int(n_beta)
+        self.device = int(device)
+        self._ctx = tbsci_create(M, n_alpha, n_beta, h, eri, alpha, beta, device)
+        self.l_alpha, self.l_beta, self.n_det = tbsci_dims(self._ctx)
+
+    @classmethod
+    def from_problem(cls, prob, device=0):
+        return cls(prob.M, prob.n_alpha, prob.n_beta, prob.h, prob.eri, prob.alpha, prob.beta,
+                   device)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            tbsci_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def _dev(self):
+        return torch.device("cuda", self.device)
+
+    def sigma(self, C, out=None, precision=TBSCI_FP64, stream=None):
+        dt = torch.float64 if precision == TBSCI_FP64 else torch.float32
+        if C.dtype != dt or not C.is_cuda or not C.is_contiguous() or C.numel() != self.n_det:
+            raise ValueError("C must be a contiguous device tensor of n_det elements of the "
+                             "precision's type")
+        if out is None:
+            out = torch.empty((self.l_alpha, self.l_beta), dtype=dt, device=C.device)
+        elif out.dtype != dt or not out.is_contiguous() or out.numel() != self.n_det:
+            raise ValueError("out must be a contiguous tensor like C")
+        tbsci_sigma(self._ctx, C, out, precision, stream)
+        return out
+
+    def diag(self, stream=None):
+        D = torch.empty((self.l_alpha, self.l_beta), dtype=torch.float64, device=self._dev())
+        tbsci_diag(self._ctx, D, stream)
+        return D
+
+    def davidson(self, n_max=8, max_iter=200, precision=TBSCI_FP64, tol_resid=1e-6,
+                 tol_energy=0.0, fp32_switch_resid=1e-4, precond_floor=1e-8, guess=None,
+                 want_vector=True, stream=None):
+        o = tbsci_davidson_default_opts()
+        o.n_max, o.max_iter, o.precision = n_max, max_iter, precision
+        o.tol_resid, o.tol_energy = tol_resid, tol_energy
+        o.fp32_switch_resid, o.precond_floor = fp32_switch_resid, precond_floor
+        if guess is not None and (guess.dtype != torch.float64 or guess.numel() != self.n_det):
+            raise ValueError("guess must be an FP64 device tensor of n_det elements")
+        X = torch.empty((self.l_alpha, self.l_beta), dtype=torch.float64,
+                        device=self._dev()) if want_vector else None
+        rc, info = tbsci_davidson(self._ctx, o, guess, X, stream)
+        d = info.as_dict()
+        d["status"] = rc
+        return d, X
+
+    def string_index(self, spin):
+        return tbsci_string_index(self._ctx, spin, self.l_alpha if spin == 0 else self.l_beta)
+
+    def lookup(self, spin, queries, stream=None):
+        out = torch.empty(queries.numel(), dtype=torch.int32, device=queries.device)
+        tbsci_lookup(self._ctx, spin, queries, out, stream)
+        return out
+
+    def get_list(self, spin, kind):
+        return tbsci_get_list(self._ctx, spin, kind, self.l_alpha if spin == 0 else self.l_beta)

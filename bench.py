@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the TPB sigma build sigma = H*C on one MI355X.
+
+Workload: the selected TPB space with M = 16 spatial orbitals,
+N_alpha = N_beta = 8, the 3,000 lowest-ranked alpha and beta strings of the
+12,870 (ranking: sum of occupied h_pp plus seeded N(0, 0.1) noise), i.e.
+9.0e6 determinants; integrals from seed 1002, selection seed 2002.
+
+A step is one FP64 sigma build over the whole space (all three kernels),
+with C resident in HBM.  ``value`` is determinants per second,
+n_det * steps / elapsed.  Also reported in the same JSON line: the FP32
+sigma rate, Davidson time to solution in FP64 and in mixed precision with
+|E - E_ref|, per-kernel event timings, the roofline entry of the dominant
+kernel, and the CPU oracle timed on a bounded row sample on the host cores.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_gbs": 8000.0,
+    "fp64_tflops": 78.6,   # FP64 vector and FP64 dense MFMA
+    "fp32_mfma_tflops": 157.3,
+    "fp32_vector_tflops": 157.3,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sel_m16")
+    ap.add_argument("--no-davidson", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (one process holds the whole CI "
+              "vector); --gpus must be 1.", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2503_10335_amd import tbsci as T
+    from paper_2503_10335_amd import workloads as W
+
+    if not os.path.exists(T.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    T.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+
+    prob = W.config(args.workload)
+    t0 = time.perf_counter()
+    ctx = T.Context.from_problem(prob, device=0)
+    create_s = time.perf_counter() - t0
+    n_det = ctx.n_det
+    print(f"# workload {args.workload}: l_alpha={ctx.l_alpha} l_beta={ctx.l_beta} "
+          f"n_det={n_det} create {create_s:.3f}s", file=sys.stderr, flush=True)
+
+    C64 = torch.from_numpy(W.random_vector(ctx.l_alpha, ctx.l_beta, seed=7)).to(dev)
+    S64 = torch.empty_like(C64)
+    C32 = C64.float()
+    S32 = torch.empty_like(C32)
+    stream = torch.cuda.current_stream()
+
+    def timed(C, S, prec, steps, warmup):
+        for _ in range(warmup):
+            ctx.sigma(C, out=S, precision=prec)
+        torch.cuda.synchronize()
+        T.tbsci_timing_enable(ctx.handle, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.sigma(C, out=S, precision=prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kernels = [T.tbsci_timing_read(ctx.handle, k, prec) for k in range(T.TBSCI_N_KERNELS)]
+        T.tbsci_timing_enable(ctx.handle, False)
+        return el, kernels
+
+    el64, k64 = timed(C64, S64, T.TBSCI_FP64, args.steps, args.warmup)
+    el32, k32 = timed(C32, S32, T.TBSCI_FP32, args.steps, args.warmup)
+    value = n_det * args.steps / el64
+    print(f"# fp64 sigma {1e3 * el64 / args.steps:.3f} ms/step, fp32 "
+          f"{1e3 * el32 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+
+    def kernel_table(ks, prec):
+        out = {}
+        for k in ks:
+            avg_s = k["total_ms"] / max(k["launches"], 1) * 1e-3
+            out[k["name"]] = dict(avg_ms=avg_s * 1e3, launches=k["launches"],
+                                  alg_tflops=k["flops"] / avg_s / 1e12 if avg_s > 0 else None,
+                                  compulsory_gbs=k["bytes"] / avg_s / 1e9 if avg_s > 0 else None,
+                                  flops_per_launch=k["flops"], bytes_per_launch=k["bytes"])
+        return out
+
+    kt64 = kernel_table(k64, T.TBSCI_FP64)
+    kt32 = kernel_table(k32, T.TBSCI_FP32)
+    dom = max(k64, key=lambda k: k["total_ms"])
+    dom_avg = dom["total_ms"] / dom["launches"] * 1e-3
+    achieved = dom["flops"] / dom_avg / 1e12
+    roofline = {
+        "kernel": dom["name"],
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": PEAK["fp64_tflops"],
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK["fp64_tflops"],
+        "traffic": None,
+        "avg_launch_ms": dom_avg * 1e3,
+        "flops_per_launch": dom["flops"],
+    }
+
+    result = {
+        "metric": "H·C dets/s; Davidson time to 1e-6 Eh, FP32-MFMA vs FP64; p50/p99 solve latency",
+        "value": value,
+        "unit": "dets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: selected TPB space, M={prob.M}, "
+                        f"N_alpha=N_beta={prob.n_alpha}, {ctx.l_alpha} x {ctx.l_beta} strings, "
+                        f"{n_det} determinants",
+            "M": prob.M, "n_alpha": prob.n_alpha, "n_beta": prob.n_beta,
+            "l_alpha": ctx.l_alpha, "l_beta": ctx.l_beta, "n_det": n_det,
+            "parallelism": "1 GPU",
+        },
+        "fp32_sigma_dets_per_s": n_det * args.steps / el32,
+        "fp32_ms_per_step": 1e3 * el32 / args.steps,
+        "create_s": create_s,
+        "kernels_fp64": kt64,
+        "kernels_fp32": kt32,
+        "roofline": roofline,
+    }
+
+    if not args.no_davidson:
+        ref, _ = ctx.davidson(tol_resid=1e-6, n_max=8, max_iter=600, want_vector=False)
+        d64, _ = ctx.davidson(tol_resid=1e-4, n_max=8, want_vector=False)
+        dmx, _ = ctx.davidson(tol_resid=1e-4, n_max=8, precision=T.TBSCI_MIXED,
+                              fp32_switch_resid=3e-5, want_vector=False)
+        result["davidson"] = {
+            "stop": "FP64 residual norm <= 1e-4 (energy error ~ |r|^2/gap)",
+            "e_ref": ref["energy"], "ref_resid": ref["resid_norm"], "ref_iters": ref["iters"],
+            "fp64": dict(time_s=d64["t_total_s"], sigma_s=d64["t_sigma_s"], iters=d64["iters"],
+                         energy=d64["energy"], abs_err=abs(d64["energy"] - ref["energy"]),
+                         converged=d64["converged"]),
+            "mixed": dict(time_s=dmx["t_total_s"], sigma_s=dmx["t_sigma_s"], iters=dmx["iters"],
+                          iters_fp32=dmx["iters_fp32"], iters_fp64=dmx["iters_fp64"],
+                          energy=dmx["energy"], abs_err=abs(dmx["energy"] - ref["energy"]),
+                          abs_diff_vs_fp64=abs(dmx["energy"] - d64["energy"]),
+                          converged=dmx["converged"]),
+            "speedup_mixed_vs_fp64": d64["t_total_s"] / dmx["t_total_s"],
+        }
+        print(f"# davidson fp64 {d64['t_total_s']:.3f}s ({d64['iters']} it), mixed "
+              f"{dmx['t_total_s']:.3f}s ({dmx['iters_fp32']}+{dmx['iters_fp64']} it), "
+              f"E={ref['energy']:.10f}", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = min(os.cpu_count() or 1, 16)
+        sp = O.Space.of(prob)
+        Ch = C64.cpu().numpy()
+        rng = np.random.default_rng(99)
+        probe = np.sort(rng.choice(ctx.l_alpha, size=min(16, ctx.l_alpha), replace=False))
+        t0 = time.perf_counter()
+        sp.sigma(Ch, rows=probe, nthreads=threads)
+        tp = time.perf_counter() - t0
+        n_rows = int(min(ctx.l_alpha, max(len(probe), len(probe) * args.cpu_seconds / max(tp, 1e-3))))
+        rows = np.sort(rng.choice(ctx.l_alpha, size=n_rows, replace=False))
+        t0 = time.perf_counter()
+        ref_rows = sp.sigma(Ch, rows=rows, nthreads=threads)
+        tc = time.perf_counter() - t0
+        # the sample doubles as a parity check of the timed GPU sigma
+        S64h = S64.cpu().numpy()[rows]
+        err = float(np.linalg.norm(S64h - ref_rows) / np.linalg.norm(ref_rows))
+        result["cpu_baseline"] = {
+            "value": n_rows * ctx.l_beta / tc,
+            "unit": "dets/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_rows} seeded alpha rows x {ctx.l_beta} beta columns of the same "
+                      f"space ({n_rows * ctx.l_beta} determinants), FP64 determinant-driven "
+                      f"Slater-Condon oracle, {tc:.1f} s",
+            "gpu_vs_sample_rel_err": err,
+        }
+        print(f"# cpu oracle {n_rows} rows in {tc:.1f}s on {threads} threads, parity {err:.2e}",
+              file=sys.stderr, flush=True)
+
+    print(json.dumps(result), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

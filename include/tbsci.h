@@ -101,6 +101,16 @@ int tbsci_dims(const tbsci_ctx *ctx, int64_t *l_alpha, int64_t *l_beta, int64_t 
 int tbsci_sigma(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precision, void *stream);
 
 /*
+ * One or more of the three terms of sigma, for verification and
+ * measurement: terms is a bit mask, 1 = same-spin alpha (A_a C), 2 =
+ * same-spin beta (C A_b^T), 4 = opposite spin (sum (pq|rs) E^a_pq C
+ * E^b_rs^T); sigma_dev is overwritten with the sum of the selected terms
+ * (terms = 7 is tbsci_sigma).  Arguments as tbsci_sigma.
+ */
+int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precision,
+                      int terms, void *stream);
+
+/*
  * Diagonal H_KK of every determinant (Sec. II.C: the [0,0] category,
  * precomputed and stored), device double [l_alpha][l_beta], asynchronous.
  */
@@ -150,7 +160,10 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
  *   info      host, required
  * Returns TBSCI_OK, or TBSCI_E_NOTCONV with info filled when the tolerance
  * was not met.  Synchronous with respect to the host.  Allocates its
- * workspace ((2 n_max + 3) FP64 vectors, plus two FP32 vectors for MIXED).
+ * workspace ((2 n_max + 5) FP64 vectors, plus two FP32 vectors for MIXED):
+ * the basis V and its images H V, the Ritz vector, its image, the
+ * correction, and the previous Ritz direction with its image, which the
+ * restart keeps next to the Ritz vector.
  */
 int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double *guess_dev,
                    double *C_out_dev, tbsci_davidson_info *info, void *stream);
@@ -197,6 +210,35 @@ int tbsci_list_size(const tbsci_ctx *ctx, int spin, int kind, int64_t *n_entries
  */
 int tbsci_get_list(const tbsci_ctx *ctx, int spin, int kind, int64_t *row_ptr_host,
                    int32_t *entries_host, double *values_host);
+
+/* ------------------------------------------------------------------------
+ * Measurement.  Kernels of one sigma build, by index:
+ *   0  same-spin alpha sweep   (categories [2,0] and alpha parts of [1,0], [0,0])
+ *   1  same-spin beta sweep    (categories [0,2] and beta parts of [0,1], [0,0])
+ *   2  opposite-spin term      (category [1,1] and opposite-spin parts of
+ *                               [1,0], [0,1], [0,0])
+ */
+#define TBSCI_N_KERNELS 3
+
+/*
+ * enable != 0: start recording HIP events around every kernel that
+ * tbsci_sigma launches, on the caller's stream (previous records are
+ * dropped); enable == 0: stop and drop the records.
+ */
+int tbsci_timing_enable(tbsci_ctx *ctx, int enable);
+
+/*
+ * For kernel index `kernel` (0..TBSCI_N_KERNELS-1) of the given precision:
+ * total_ms = summed event time of its recorded launches, launches = their
+ * number (waits for the recorded work to finish), flops = algorithmic
+ * floating-point operations of one launch (2 per multiply-add of the
+ * defining sums, not the operations the kernel executes), bytes =
+ * compulsory device-memory bytes of one launch (C read once, sigma read and
+ * written once, lists and values read once).  name receives a static
+ * string.  Any output pointer may be NULL.
+ */
+int tbsci_timing_read(tbsci_ctx *ctx, int kernel, int precision, double *total_ms,
+                      int64_t *launches, double *flops, double *bytes, const char **name);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *tbsci_last_error(void);

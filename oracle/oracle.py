@@ -67,6 +67,8 @@ def _load():
                                           i64, ctypes.POINTER(ctypes.c_int)]
             lib.orc_space_free.argtypes = [P]
             lib.orc_sigma.argtypes = [P, P, P, P, P, P, i64, ctypes.c_int]
+            lib.orc_sigma_rowmap.restype = ctypes.c_int
+            lib.orc_sigma_rowmap.argtypes = [P, P, P, P, P, P, P, i64, ctypes.c_int]
             lib.orc_element.restype = ctypes.c_double
             lib.orc_element.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                         ctypes.c_uint64]
@@ -130,6 +132,29 @@ class Space:
             _load().orc_sigma(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(C), _ptr(out),
                               _ptr(rows), len(rows), nthreads)
         return out
+
+    def sigma_rows_from(self, rows, csub, c_rows, nthreads=0):
+        """sigma on output rows ``rows`` with C supplied only on rows ``c_rows``
+        (csub[i] = C[c_rows[i]]); every row linked to an output row must be
+        supplied, else ValueError."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        csub = np.ascontiguousarray(csub, dtype=np.float64).reshape(len(c_rows), self.lb)
+        slot = np.full(self.la, -1, dtype=np.int64)
+        slot[np.asarray(c_rows, dtype=np.int64)] = np.arange(len(c_rows))
+        out = np.empty((len(rows), self.lb))
+        rc = _load().orc_sigma_rowmap(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(csub),
+                                      _ptr(slot), _ptr(out), _ptr(rows), len(rows), nthreads)
+        if rc != 0:
+            raise ValueError("a needed row of C was not supplied")
+        return out
+
+    def linked_rows(self, rows):
+        """Alpha rows reachable from ``rows`` by zero, one or two excitations."""
+        need = set(int(r) for r in rows)
+        for kind in (1, 2):
+            ptr, ent = lists(self.alpha, self.M, kind, rows=rows)
+            need.update(int(j) for j in ent[:, 0])
+        return np.array(sorted(need), dtype=np.int64)
 
     def diag(self, rows=None, nthreads=0):
         if rows is None:
@@ -253,8 +278,9 @@ def davidson(apply_h, diag, tol=1e-8, n_max=8, max_iter=500, guess=None, floor=1
 
     Guess: unit vector on the smallest diagonal element (first on ties).
     Preconditioner t = r / (theta - H_KK), denominators below ``floor`` in
-    magnitude replaced by +-floor keeping the sign.  Gram-Schmidt twice;
-    a correction with norm < 1e-10 after orthogonalisation stops the solve.
+    magnitude replaced by +-floor keeping the sign.  The correction is
+    normalised, orthogonalised twice (Gram-Schmidt); if less than 1e-10 of
+    its norm survives, the solve stops (no new direction).
     Restart: when the basis reaches n_max vectors it collapses to the Ritz
     vector.  Returns dict(energy, x, resid, iters, converged).
     """
@@ -289,6 +315,7 @@ def davidson(apply_h, diag, tol=1e-8, n_max=8, max_iter=500, guess=None, floor=1
         small = np.abs(den) < floor
         den[small] = np.where(den[small] < 0, -floor, floor)
         t = r / den
+        t /= np.linalg.norm(t)  # the stagnation test below is relative to |t|
         for _ in range(2):
             for v in V:
                 t = t - (v @ t) * v

@@ -168,8 +168,26 @@ static int64_t lookup_det(const ospace *s, const det_t *d, int64_t *col) {
     return ia;
 }
 
+/* C rows supplied through a map: row_slot[ia] = row of Csub holding C[ia, :],
+ * or -1 if that row was not supplied (then *missing is set). */
+typedef struct {
+    const double *C;
+    const int64_t *row_slot; /* NULL: C is the full matrix */
+    int *missing;
+} cview;
+
+static double cget(const cview *v, int64_t ja, int64_t jb, int64_t lb) {
+    if (!v->row_slot) return v->C[ja * lb + jb];
+    int64_t r = v->row_slot[ja];
+    if (r < 0) {
+        *v->missing = 1;
+        return 0.0;
+    }
+    return v->C[r * lb + jb];
+}
+
 /* sigma for one output determinant (row ia, column ib) */
-static double sigma_one(const ospace *s, const double *C, int64_t ia, int64_t ib,
+static double sigma_one(const ospace *s, const cview *C, int64_t ia, int64_t ib,
                         const uint64_t *alpha, const uint64_t *beta) {
     int M = s->M;
     det_t D; D.w[0] = alpha[ia]; D.w[1] = beta[ib];
@@ -178,7 +196,7 @@ static double sigma_one(const ospace *s, const double *C, int64_t ia, int64_t ib
     int nv = 0;
     for (int X = 0; X < 2 * M; ++X) if (!so_occ(&D, M, X)) vir[nv++] = X;
     const int64_t lb = s->lb;
-    double acc = diag_element(s, &D) * C[ia * lb + ib];
+    double acc = diag_element(s, &D) * cget(C, ia, ib, lb);
     /* singles X -> A (same spin only; other spins give zero elements) */
     for (int x = 0; x < n; ++x) {
         for (int a = 0; a < nv; ++a) {
@@ -189,7 +207,7 @@ static double sigma_one(const ospace *s, const double *C, int64_t ia, int64_t ib
             so_apply(&E, M, A, 1, &sg);
             int64_t jb, ja = lookup_det(s, &E, &jb);
             if (ja < 0) continue;
-            acc += sg * single_element(s, occ, n, X, A) * C[ja * lb + jb];
+            acc += sg * single_element(s, occ, n, X, A) * cget(C, ja, jb, lb);
         }
     }
     /* doubles X<Y -> A<B */
@@ -209,7 +227,7 @@ static double sigma_one(const ospace *s, const double *C, int64_t ia, int64_t ib
                     so_apply(&E, M, A, 1, &sg);
                     int64_t jb, ja = lookup_det(s, &E, &jb);
                     if (ja < 0) continue;
-                    acc += sg * v * C[ja * lb + jb];
+                    acc += sg * v * cget(C, ja, jb, lb);
                 }
     return acc;
 }
@@ -234,9 +252,8 @@ void orc_space_free(void *p) {
 }
 
 /* sigma rows: rows == NULL -> all alpha rows; out is [nrows][lb] */
-void orc_sigma(void *p, const uint64_t *alpha, const uint64_t *beta, const double *C,
-               double *out, const int64_t *rows, int64_t nrows, int nthreads) {
-    ospace *s = (ospace *)p;
+static void sigma_rows(ospace *s, const uint64_t *alpha, const uint64_t *beta, const cview *v,
+                       double *out, const int64_t *rows, int64_t nrows, int nthreads) {
     int64_t nr = rows ? nrows : s->la;
     int64_t total = nr * s->lb;
 #ifdef _OPENMP
@@ -246,8 +263,26 @@ void orc_sigma(void *p, const uint64_t *alpha, const uint64_t *beta, const doubl
     for (int64_t t = 0; t < total; ++t) {
         int64_t r = t / s->lb, ib = t % s->lb;
         int64_t ia = rows ? rows[r] : r;
-        out[t] = sigma_one(s, C, ia, ib, alpha, beta);
+        out[t] = sigma_one(s, v, ia, ib, alpha, beta);
     }
+}
+
+void orc_sigma(void *p, const uint64_t *alpha, const uint64_t *beta, const double *C,
+               double *out, const int64_t *rows, int64_t nrows, int nthreads) {
+    int missing = 0;
+    cview v = {C, NULL, &missing};
+    sigma_rows((ospace *)p, alpha, beta, &v, out, rows, nrows, nthreads);
+}
+
+/* As orc_sigma, with C given only for some rows: Csub[row_slot[ia]][:] = C[ia][:].
+ * Returns 0, or -1 if an output row needed a C row that was not supplied. */
+int orc_sigma_rowmap(void *p, const uint64_t *alpha, const uint64_t *beta, const double *Csub,
+                     const int64_t *row_slot, double *out, const int64_t *rows, int64_t nrows,
+                     int nthreads) {
+    int missing = 0;
+    cview v = {Csub, row_slot, &missing};
+    sigma_rows((ospace *)p, alpha, beta, &v, out, rows, nrows, nthreads);
+    return missing ? -1 : 0;
 }
 
 /* <D_I|H|D_J> for arbitrary determinants (generic Slater-Condon). */

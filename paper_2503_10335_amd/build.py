@@ -16,6 +16,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 vector ops are disabled on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-munsafe-fp-atomics",  # hardware float atomics (LDS and global adds)
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -80,6 +80,7 @@ void free_spin(Spin &s) {
 void destroy_ctx(Ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    timing_clear(*c);
     for (auto &s : c->sp) free_spin(s);
     void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work};
     for (void *p : ptrs)
@@ -220,6 +221,22 @@ int tbsci_sigma(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precisio
     });
 }
 
+int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precision,
+                      int terms, void *stream) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        Ctx *c = ctx_of(ctx);
+        if (precision != TBSCI_FP64 && precision != TBSCI_FP32)
+            throw Error(TBSCI_E_INVAL, "precision must be TBSCI_FP64 or TBSCI_FP32");
+        if (terms < 0 || terms > 7) throw Error(TBSCI_E_INVAL, "terms must be a mask in 0..7");
+        check_dev(C_dev, c->device, "C");
+        check_dev(sigma_dev, c->device, "sigma");
+        if (C_dev == sigma_dev) throw Error(TBSCI_E_INVAL, "C and sigma must not alias");
+        launch_sigma(*c, C_dev, sigma_dev, precision, (hipStream_t)stream, terms);
+        return TBSCI_OK;
+    });
+}
+
 int tbsci_diag(tbsci_ctx *ctx, double *diag_dev, void *stream) {
     return guarded([&]() -> int {
         check_ctx(ctx);
@@ -312,6 +329,60 @@ int tbsci_get_list(const tbsci_ctx *ctx, int spin, int kind, int64_t *row_ptr_ho
                 o[5] = ((w >> 24) & 1) ? -1 : 1;
             }
         }
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_timing_enable(tbsci_ctx *ctx, int enable) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        Ctx *c = ctx_of(ctx);
+        timing_clear(*c);
+        c->timing = enable != 0;
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_timing_read(tbsci_ctx *ctx, int kernel, int precision, double *total_ms,
+                      int64_t *launches, double *flops, double *bytes, const char **name) {
+    static const char *names[TBSCI_N_KERNELS] = {"same_spin_alpha_sweep", "same_spin_beta_sweep",
+                                                 "opposite_spin"};
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        if (kernel < 0 || kernel >= TBSCI_N_KERNELS) throw Error(TBSCI_E_INVAL, "no such kernel");
+        if (precision != TBSCI_FP64 && precision != TBSCI_FP32)
+            throw Error(TBSCI_E_INVAL, "precision must be TBSCI_FP64 or TBSCI_FP32");
+        Ctx *c = ctx_of(ctx);
+        double ms = 0.0;
+        int64_t n = 0;
+        for (auto &t : c->timed) {
+            if (t.precision != precision) continue;
+            TB_HIP(hipEventSynchronize(t.ev[kernel + 1]));
+            float x = 0.f;
+            TB_HIP(hipEventElapsedTime(&x, t.ev[kernel], t.ev[kernel + 1]));
+            ms += x;
+            ++n;
+        }
+        const Spin &A = c->sp[0], &B = c->sp[1];
+        const double la = (double)A.l, lb = (double)B.l, nd = la * lb;
+        const double sz = precision == TBSCI_FP64 ? 8.0 : 4.0;
+        double f = 0.0, b = 0.0;
+        if (kernel == 0) {
+            f = 2.0 * (double)A.n_a * lb;
+            b = 2.0 * nd * sz + 8.0 * (la + 1) + (4.0 + sz) * (double)A.n_a;
+        } else if (kernel == 1) {
+            f = 2.0 * (double)B.n_a * la;
+            b = 3.0 * nd * sz + 8.0 * (lb + 1) + (4.0 + sz) * (double)B.n_a;
+        } else {
+            f = 2.0 * (double)A.n_s * (double)B.n_s;
+            b = 3.0 * nd * sz + 8.0 * (la + lb + 2) + 8.0 * (double)(A.n_s + B.n_s) +
+                sz * (double)c->P * c->P;
+        }
+        if (total_ms) *total_ms = ms;
+        if (launches) *launches = n;
+        if (flops) *flops = f;
+        if (bytes) *bytes = b;
+        if (name) *name = names[kernel];
         return TBSCI_OK;
     });
 }

@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -119,6 +121,22 @@ __global__ __launch_bounds__(kB) void k_ritz(int64_t n, int64_t lb, int M, VecLi
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// xo = sum_i z[i] V[i], wo = sum_i z[i] W[i]
+__global__ __launch_bounds__(kB) void k_lincomb2(int64_t n, VecList V, VecList W, int k,
+                                                 const double *__restrict__ z,
+                                                 double *__restrict__ xo,
+                                                 double *__restrict__ wo) {
+    for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t < n; t += (int64_t)gridDim.x * kB) {
+        double xv = 0.0, wv = 0.0;
+        for (int i = 0; i < k; ++i) {
+            xv += z[i] * V.p[i][t];
+            wv += z[i] * W.p[i][t];
+        }
+        xo[t] = xv;
+        wo[t] = wv;
+    }
 }
 
 __global__ void k_unit(int64_t n, int64_t at, double *__restrict__ v) {
@@ -265,6 +283,7 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
         W[i] = ws.get(n);
     }
     double *X = ws.get(n), *WX = ws.get(n), *T = ws.get(n);
+    double *XP = ws.get(n), *WXP = ws.get(n);  // previous Ritz direction for the restart
     float *T32 = nullptr, *S32 = nullptr;
     if (mixed) {
         T32 = (float *)ws.get((n + 1) / 2);
@@ -277,6 +296,8 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
     Events ev;
 
     memset(&info, 0, sizeof(info));
+    const char *tr_env = getenv("TBSCI_DAVIDSON_TRACE");  // per-iteration trace on stderr
+    const bool trace = tr_env && tr_env[0] && tr_env[0] != '0';
     double t_sigma = 0.0;
     bool fp32 = mixed;
     auto sigma = [&](const double *in, double *out) {
@@ -339,7 +360,7 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
     }
     TB_HIP(hipGetLastError());
 
-    std::vector<double> G((size_t)nmax * nmax, 0.0), col(kMaxVec), w, Z;
+    std::vector<double> G((size_t)nmax * nmax, 0.0), col(kMaxVec), w, Z, yprev;
     int k = 1;
     sigma(V[0], W[0]);
     multidot(V, 1, W[0], col.data());
@@ -359,6 +380,9 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
         theta = w[lo];
         std::vector<double> y(k);
         for (int i = 0; i < k; ++i) y[i] = Z[i * k + lo];
+        std::vector<double> yp = yprev;  // previous Ritz coefficients in this basis
+        yp.resize(k, 0.0);
+        yprev = y;
         TB_HIP(hipMemcpyAsync(ydev, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
         k_ritz<<<gb, kB, 0, st>>>(n, lb, c.M, vl(V, k), vl(W, k), k, ydev, theta, o.precond_floor,
                                   c.sp[0].str, c.sp[0].dsame, c.sp[1].dsame, c.sp[1].jocc, X, WX, T,
@@ -368,15 +392,20 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
         TB_HIP(hipMemcpyAsync(&r2, dots, sizeof(double), hipMemcpyDeviceToHost, st));
         TB_HIP(hipStreamSynchronize(st));
         rn = std::sqrt(std::max(r2, 0.0));
+        if (trace)
+            fprintf(stderr, "tbsci davidson: sigma %d k %d %s theta %.15f resid %.3e\n", info.iters, k,
+                    fp32 ? "fp32" : "fp64", theta, rn);
 
         if (fp32) {
-            if (rn < 0.9 * best_rn) {
+            // the FP32 phase ends at fp32_switch_resid, or when the residual has
+            // not improved by 2% for 20 sigma builds (FP32 rounding floor)
+            if (rn < 0.98 * best_rn) {
                 best_rn = rn;
                 since_best = 0;
             } else {
                 ++since_best;
             }
-            if (rn <= o.fp32_switch_resid || since_best >= 5 || info.iters >= o.max_iter / 2) {
+            if (rn <= o.fp32_switch_resid || since_best >= 20 || info.iters >= o.max_iter / 2) {
                 // correction phase: restart from the Ritz vector with FP64 sigma builds
                 fp32 = false;
                 TB_HIP(hipMemcpyAsync(V[0], X, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -385,6 +414,7 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
                 G[0] = col[0];
                 k = 1;
                 theta = col[0];
+                yprev.clear();
                 continue;
             }
         } else if (rn <= o.tol_resid &&
@@ -393,13 +423,75 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
             break;
         }
         if (info.iters >= o.max_iter) break;
-        if (k >= nmax) {  // collapse restart to the Ritz vector
-            TB_HIP(hipMemcpyAsync(V[0], X, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-            TB_HIP(hipMemcpyAsync(W[0], WX, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-            G[0] = theta;
-            k = 1;
+        if (k >= nmax) {
+            // restart: keep the Ritz vector x = V y and the part of the
+            // previous Ritz vector orthogonal to it, z = yp - (yp.y) y
+            std::vector<double> z(k);
+            double dz = 0.0, nz = 0.0;
+            for (int i = 0; i < k; ++i) dz += yp[i] * y[i];
+            for (int i = 0; i < k; ++i) {
+                z[i] = yp[i] - dz * y[i];
+                nz += z[i] * z[i];
+            }
+            nz = std::sqrt(nz);
+            std::swap(V[0], X);
+            std::swap(W[0], WX);
+            bool two = false;
+            if (nz > 1e-8) {
+                for (int i = 0; i < k; ++i) z[i] /= nz;
+                TB_HIP(hipMemcpyAsync(ydev, z.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+                // X / WX now hold the old V[0] / W[0]: V and W of the old basis
+                // are read through a list that maps slot 0 to them
+                std::vector<double *> Vo(V.begin(), V.begin() + k), Wo(W.begin(), W.begin() + k);
+                Vo[0] = X;
+                Wo[0] = WX;
+                k_lincomb2<<<1024, kB, 0, st>>>(n, vl(Vo, k), vl(Wo, k), k, ydev, XP, WXP);
+                TB_HIP(hipGetLastError());
+                TB_HIP(hipStreamSynchronize(st));  // z lives on the host stack
+                // z is a difference of nearly equal vectors near convergence, so
+                // V z is re-orthogonalised against x on the device (twice), with
+                // the same combination applied to its image
+                std::vector<double *> v0{V[0]}, w0{W[0]}, xp{XP};
+                for (int pass = 0; pass < 2; ++pass) {
+                    multidot(v0, 1, XP, nullptr);
+                    k_sub_proj<<<1024, kB, 0, st>>>(n, vl(v0, 1), 1, dots, XP);
+                    k_sub_proj<<<1024, kB, 0, st>>>(n, vl(w0, 1), 1, dots, WXP);
+                }
+                double n2;
+                multidot(xp, 1, XP, &n2);
+                if (std::sqrt(std::max(n2, 0.0)) > 1e-8) {
+                    k_scale_by_rnorm<<<1024, kB, 0, st>>>(n, dots, XP);
+                    k_scale_by_rnorm<<<1024, kB, 0, st>>>(n, dots, WXP);
+                    double g0[2], g1[2];
+                    std::vector<double *> ws2{W[0], WXP};
+                    multidot(ws2, 2, V[0], g0);  // x.Wx, x.Wxp
+                    multidot(ws2, 2, XP, g1);    // xp.Wx, xp.Wxp
+                    std::swap(V[1], XP);
+                    std::swap(W[1], WXP);
+                    G[0] = g0[0];
+                    G[1] = g0[1];
+                    G[nmax] = g1[0];
+                    G[nmax + 1] = g1[1];
+                    k = 2;
+                    yprev.assign({1.0, 0.0});
+                    two = true;
+                }
+            }
+            if (!two) {
+                std::vector<double *> v0{V[0]};
+                multidot(v0, 1, W[0], col.data());
+                G[0] = col[0];
+                k = 1;
+                yprev.assign({1.0});
+            }
         }
-        // two Gram-Schmidt passes against V[0..k)
+        // normalise t (the drop test below is relative), then two
+        // Gram-Schmidt passes against V[0..k)
+        {
+            std::vector<double *> tv{T};
+            multidot(tv, 1, T, nullptr);
+            k_scale_by_rnorm<<<1024, kB, 0, st>>>(n, dots, T);
+        }
         for (int pass = 0; pass < 2; ++pass) {
             multidot(V, k, T, nullptr);
             k_sub_proj<<<1024, kB, 0, st>>>(n, vl(V, k), k, dots, T);

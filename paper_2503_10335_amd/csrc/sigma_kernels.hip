@@ -11,12 +11,22 @@
 // split is exact because the projector onto the TPB space is the tensor
 // product of the alpha and beta projectors and the opposite-spin operator
 // is a sum of products of one-spin operators.
+//
+// Kernels of one sigma build:
+//   opposite spin : per output alpha row, gather the rows of C linked by
+//                   alpha single excitations, multiply by the folded (pq|rs)
+//                   block on MFMA, scatter through the beta single lists
+//                   into the output row held in LDS (LDS atomics);
+//   alpha sweep   : sparse rows of A_a times rows of C, one XCD per column
+//                   panel so each XCD's L2 holds its panel of C;
+//   beta sweep    : the same kernel on C^T, then a transpose-add.
 #include "tbsci_internal.hpp"
 
 namespace tbsci {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kXcd = 8;  // MI355X: 8 XCDs; workgroups are dealt to XCDs round-robin
 
 template <typename T>
 struct Vals;
@@ -31,53 +41,337 @@ struct Vals<float> {
     static const float *V(const Ctx &c) { return c.V32; }
 };
 
-// alpha-alpha row sweep: sigma[I, :] = sum_J A_a[I, J] C[J, :] (overwrites).
-// One block per (row I, column block); list entries are block-uniform, the
-// C rows are read coalesced.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_aa_sweep(int64_t lb, int64_t ncb,
-                                                     const int64_t *__restrict__ a_ptr,
-                                                     const int32_t *__restrict__ a_col,
-                                                     const T *__restrict__ a_val,
-                                                     const T *__restrict__ C, T *__restrict__ S) {
-    const int64_t I = blockIdx.x / ncb;
-    const int64_t col = (blockIdx.x - I * ncb) * kBlock + threadIdx.x;
-    if (col >= lb) return;
-    T acc = 0;
-    const int64_t e1 = a_ptr[I + 1];
-    for (int64_t e = a_ptr[I]; e < e1; ++e) acc += a_val[e] * C[(int64_t)a_col[e] * lb + col];
-    S[I * lb + col] = acc;
-}
+// ---------------------------------------------------------------- sweeps
 
-// beta-beta column sweep: sigma[I, I'] += sum_J' A_b[I', J'] C[I, J'].
-// Thread per column I', R alpha rows per block so each list entry is reused.
-template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void k_bb_sweep(int64_t la, int64_t lb, int64_t ncb,
-                                                     const int64_t *__restrict__ b_ptr,
-                                                     const int32_t *__restrict__ b_col,
-                                                     const T *__restrict__ b_val,
-                                                     const T *__restrict__ C, T *__restrict__ S) {
-    const int64_t rb = blockIdx.x / ncb;
-    const int64_t Ip = (blockIdx.x - rb * ncb) * kBlock + threadIdx.x;
-    if (Ip >= lb) return;
-    const int64_t I0 = rb * R;
-    T acc[R];
+// Y[I][c] (+)= sum_e val[e] * X[col[e]][c].  Block = 4 waves = 4 output rows
+// x 64 columns; the list of a row is wave-uniform, X rows are read
+// coalesced.  Column tiles belong to XCDs round-robin (tile t on XCD t % 8)
+// and an XCD walks its tiles one after the other, so its working set is one
+// panel of X (nrows x 64 columns).
+template <typename T, bool ACC>
+__global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t ncols, int64_t ntiles,
+                                                      int64_t nrb, int64_t tiles_per_xcd,
+                                                      const int64_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val,
+                                                      const T *__restrict__ X, T *__restrict__ Y) {
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b % kXcd, local = b / kXcd;
+    const int64_t tl = local / nrb, rb = local - tl * nrb;
+    const int64_t tile = xcd + kXcd * tl;
+    if (tl >= tiles_per_xcd || tile >= ntiles) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t I = rb * 4 + wave;
+    if (I >= nrows) return;
+    const int64_t c = tile * 64 + lane;
+    const bool ok = c < ncols;
+    const T *__restrict__ Xc = X + (ok ? c : 0);
+    const int64_t e0 = ptr[I], e1 = ptr[I + 1];
+    T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    int64_t e = e0;
+    for (; e + 8 <= e1; e += 8) {
+        int32_t j[8];
+        T v[8], x[8];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0;
-    const int64_t e1 = b_ptr[Ip + 1];
-    for (int64_t e = b_ptr[Ip]; e < e1; ++e) {
-        const int64_t j = b_col[e];
-        const T v = b_val[e];
+        for (int u = 0; u < 8; ++u) {
+            j[u] = col[e + u];
+            v[u] = val[e + u];
+        }
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (I0 + r < la) acc[r] += v * C[(I0 + r) * lb + j];
+        for (int u = 0; u < 8; ++u) x[u] = Xc[(int64_t)j[u] * ncols];
+        acc0 += v[0] * x[0];
+        acc1 += v[1] * x[1];
+        acc2 += v[2] * x[2];
+        acc3 += v[3] * x[3];
+        acc0 += v[4] * x[4];
+        acc1 += v[5] * x[5];
+        acc2 += v[6] * x[6];
+        acc3 += v[7] * x[7];
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (I0 + r < la) S[(I0 + r) * lb + Ip] += acc[r];
+    for (; e < e1; ++e) acc0 += val[e] * Xc[(int64_t)col[e] * ncols];
+    const T acc = (acc0 + acc1) + (acc2 + acc3);
+    if (ok) {
+        if (ACC)
+            Y[I * ncols + c] += acc;
+        else
+            Y[I * ncols + c] = acc;
+    }
 }
 
-// Opposite-spin term, direct double sum:
+// out[c][r] (+)= in[r][c] for an R x Cn row-major input; 32 x 32 tiles via LDS.
+template <typename T, bool ADD>
+__global__ __launch_bounds__(kBlock) void k_transpose(int64_t R, int64_t Cn, int64_t ntc,
+                                                      const T *__restrict__ in, T *__restrict__ out) {
+    __shared__ T tile[32][33];
+    const int64_t tr = blockIdx.x / ntc, tc = blockIdx.x - tr * ntc;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t r = tr * 32 + i, c = tc * 32 + tx;
+        if (r < R && c < Cn) tile[i][tx] = in[r * Cn + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t c = tc * 32 + i, r = tr * 32 + tx;
+        if (r < R && c < Cn) {
+            const T v = tile[tx][i];
+            if (ADD)
+                out[c * R + r] += v;
+            else
+                out[c * R + r] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------- opposite spin
+
+template <typename T>
+struct Mfma;
+// Operand layouts of the 16x16x4 MFMAs (lane l, 0..63): A[m][k] with
+// m = l%16, k = l/16; B[k][n] with k = l/16, n = l%16.  Accumulator register
+// r of lane l holds D[row(l, r)][l%16]; the row order differs by type.
+template <>
+struct Mfma<double> {
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<float> {
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int kTW = 32;         // source beta columns per tile (2 MFMA N-subtiles)
+constexpr int kNS = kTW / 16;
+constexpr int kXS = kTW + 1;    // LDS row stride of the X and Y tiles
+
+struct AbLds {
+    size_t row, aj, bp, x, y, total;
+};
+
+// LDS layout of k_ab_gemm (bytes)
+inline AbLds ab_lds(int64_t lb, int kmax, int P, size_t sz, bool lds_row) {
+    AbLds L{};
+    size_t o = 0;
+    auto take = [&](size_t n) {
+        const size_t at = o;
+        o += (n + 15) & ~size_t(15);
+        return at;
+    };
+    L.row = take(lds_row ? (size_t)lb * sz : 0);
+    L.aj = take((size_t)kmax * 4);
+    L.bp = take((kTW + 1) * 8);
+    L.x = take((size_t)kmax * kXS * sz);
+    L.y = take((size_t)P * kXS * sz);
+    L.total = o;
+    return L;
+}
+
+// One block per output alpha row I; wave w owns MFMA M-tile w (pairs
+// rs = 16w .. 16w+15), so blockDim = 64 * ceil(P/16).
+//
+//   X[k][c]  = C[J_k][c]                     (gather, k over the alpha links of I)
+//   Y[rs][c] = sum_k s_k V[pq_k][rs] X[k][c]  (MFMA, K = links, M = folded pairs)
+//   row[I']  += s * Y[pair][J']  for every link (I', pair, s) of J' in the
+//               beta single lists (the lists are symmetric: the links of J'
+//               are the sources of I')
+//
+// KS = maximum number of 4-deep MFMA k-steps (links padded to 4 * KS).
+// With LDS_ROW the output row lives in LDS and is added to sigma at the
+// end; otherwise the scatter adds into sigma with global atomics.
+template <typename T, int KS, bool LDS_ROW>
+__global__ __launch_bounds__(1024) void k_ab_gemm(int64_t lb, int P, AbLds L,
+                                                  const int64_t *__restrict__ sa_ptr,
+                                                  const Ent *__restrict__ sa_ent,
+                                                  const int64_t *__restrict__ sb_ptr,
+                                                  const Ent *__restrict__ sb_ent,
+                                                  const T *__restrict__ V, const T *__restrict__ C,
+                                                  T *__restrict__ S) {
+    using M = Mfma<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *row = (T *)(smem + L.row);
+    int32_t *aj = (int32_t *)(smem + L.aj);
+    int64_t *bp = (int64_t *)(smem + L.bp);
+    T *xt = (T *)(smem + L.x);
+    T *yt = (T *)(smem + L.y);
+
+    const int64_t I = blockIdx.x;
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t a0 = sa_ptr[I];
+    const int K = (int)(sa_ptr[I + 1] - a0);
+    const int nks = (K + 3) >> 2, Kp = nks * 4;
+
+    if (LDS_ROW)
+        for (int64_t i = tid; i < lb; i += nthr) row[i] = T(0);
+    for (int k = tid; k < Kp; k += nthr) aj[k] = k < K ? sa_ent[a0 + k].j : -1;
+
+    // A fragments of this wave's M-tile: lane holds U[k = 4ks + lane/16][m = lane%16]
+    T ua[KS];
+    {
+        const int m = wave * 16 + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            T a = T(0);
+            const int k = 4 * ks + (lane >> 4);
+            if (ks < nks && k < K && m < P) {
+                const Ent e = sa_ent[a0 + k];
+                const T v = V[(int64_t)(e.o >> 16) * P + m];
+                a = ((e.o >> 12) & 1u) ? -v : v;
+            }
+            ua[ks] = a;
+        }
+    }
+    __syncthreads();
+
+    const int64_t ntile = (lb + kTW - 1) / kTW;
+    for (int64_t t = 0; t < ntile; ++t) {
+        const int64_t j0 = t * kTW;
+        // gather X tile and the tile's beta list pointers
+        for (int i = tid; i < Kp * kTW; i += nthr) {
+            const int k = i / kTW, cc = i - k * kTW;
+            const int32_t J = aj[k];
+            T v = T(0);
+            if (J >= 0 && j0 + cc < lb) v = C[(int64_t)J * lb + j0 + cc];
+            xt[k * kXS + cc] = v;
+        }
+        for (int i = tid; i <= kTW; i += nthr) bp[i] = sb_ptr[j0 + i < lb ? j0 + i : lb];
+        __syncthreads();
+        // MFMA: Y tile rows of this wave's M-tile
+        if (wave * 16 < P) {
+            typename M::acc_t acc[kNS];
+#pragma unroll
+            for (int ns = 0; ns < kNS; ++ns) acc[ns] = typename M::acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < nks) {
+                    const int k = 4 * ks + (lane >> 4);
+#pragma unroll
+                    for (int ns = 0; ns < kNS; ++ns)
+                        acc[ns] = M::mma(ua[ks], xt[k * kXS + ns * 16 + (lane & 15)], acc[ns]);
+                }
+            }
+#pragma unroll
+            for (int ns = 0; ns < kNS; ++ns)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = wave * 16 + M::row(lane, r);
+                    if (m < P) yt[m * kXS + ns * 16 + (lane & 15)] = acc[ns][r];
+                }
+        }
+        __syncthreads();
+        // scatter through the beta links of the tile's source columns
+        const int64_t e0 = bp[0], e1 = bp[kTW];
+        for (int64_t e = e0 + tid; e < e1; e += nthr) {
+            int lo = 0, hi = kTW;  // column: bp[lo] <= e < bp[lo+1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (bp[mid] <= e)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const Ent eb = sb_ent[e];
+            T v = yt[(int)(eb.o >> 16) * kXS + lo];
+            if ((eb.o >> 12) & 1u) v = -v;
+            if (LDS_ROW)
+                atomicAdd(&row[eb.j], v);
+            else
+                atomicAdd(&S[I * lb + eb.j], v);
+        }
+        __syncthreads();
+    }
+    if (LDS_ROW)
+        for (int64_t i = tid; i < lb; i += nthr) S[I * lb + i] += row[i];
+}
+
+// ---------------------------------------------------------------- driver
+
+template <typename T>
+T *workspace(Ctx &c, int which) {
+    const size_t nd = (size_t)(c.sp[0].l * c.sp[1].l);
+    const size_t need = 2 * nd * sizeof(double);
+    if (c.work_bytes < need) {
+        if (c.work) TB_HIP(hipFree(c.work));
+        c.work = nullptr;
+        c.work_bytes = 0;
+        TB_HIP(hipMalloc(&c.work, need));
+        c.work_bytes = need;
+    }
+    return (T *)c.work + which * nd;
+}
+
+template <typename T>
+void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st) {
+    const int64_t nrows = s.l;
+    const int64_t ntiles = (ncols + 63) / 64, nrb = (nrows + 3) / 4;
+    const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
+    const unsigned grid = (unsigned)(kXcd * tpx * nrb);
+    if (acc)
+        k_row_sweep<T, true><<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr, s.a_col,
+                                                      Vals<T>::a(s), X, Y);
+    else
+        k_row_sweep<T, false><<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr,
+                                                       s.a_col, Vals<T>::a(s), X, Y);
+    TB_HIP(hipGetLastError());
+}
+
+template <typename T, bool ADD>
+void launch_transpose(int64_t R, int64_t Cn, const T *in, T *out, hipStream_t st) {
+    const int64_t ntr = (R + 31) / 32, ntc = (Cn + 31) / 32;
+    k_transpose<T, ADD><<<(unsigned)(ntr * ntc), kBlock, 0, st>>>(R, Cn, ntc, in, out);
+    TB_HIP(hipGetLastError());
+}
+
+template <typename T, int KS>
+void launch_ab_ks(Ctx &c, const T *C, T *S, bool lds_row, hipStream_t st) {
+    const Spin &A = c.sp[0], &B = c.sp[1];
+    const int P = c.P;
+    const int nw = (P + 15) / 16;
+    const AbLds L = ab_lds(B.l, 4 * KS, P, sizeof(T), lds_row);
+    if (lds_row) {
+        auto f = k_ab_gemm<T, KS, true>;
+        TB_HIP(hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)L.total));
+        f<<<(unsigned)A.l, 64 * nw, L.total, st>>>(B.l, P, L, A.s_ptr, A.s_ent, B.s_ptr, B.s_ent,
+                                                   Vals<T>::V(c), C, S);
+    } else {
+        auto f = k_ab_gemm<T, KS, false>;
+        TB_HIP(hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)L.total));
+        f<<<(unsigned)A.l, 64 * nw, L.total, st>>>(B.l, P, L, A.s_ptr, A.s_ent, B.s_ptr, B.s_ent,
+                                                   Vals<T>::V(c), C, S);
+    }
+    TB_HIP(hipGetLastError());
+}
+
+constexpr size_t kLdsMax = 160 * 1024;
+
+// opposite-spin term; returns false if this shape needs the direct kernel
+template <typename T>
+bool launch_ab(Ctx &c, const T *C, T *S, bool lds_row, hipStream_t st) {
+    const int ks = (c.sp[0].max_s + 3) / 4;
+    if (c.P > 256 || ks > 32) return false;
+#define TB_KS(n)                                        \
+    if (ks <= n) {                                      \
+        launch_ab_ks<T, n>(c, C, S, lds_row, st);       \
+        return true;                                    \
+    }
+    TB_KS(4) TB_KS(8) TB_KS(12) TB_KS(16) TB_KS(20) TB_KS(24) TB_KS(28) TB_KS(32)
+#undef TB_KS
+    return false;
+}
+
+// Opposite-spin term, direct double sum (general fallback):
 // sigma[I, I'] += sum_{k in L_a(I)} sum_{l in L_b(I')} s_k s_l V[pair_k][pair_l] C[J_k, J'_l]
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ab_direct(int64_t lb, int64_t ncb, int P,
@@ -108,30 +402,63 @@ __global__ __launch_bounds__(kBlock) void k_ab_direct(int64_t lb, int64_t ncb, i
 }
 
 template <typename T>
-void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st) {
+void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     const int64_t la = A.l, lb = B.l;
-    const int64_t ncb = (lb + kBlock - 1) / kBlock;
-    k_aa_sweep<T><<<(unsigned)(la * ncb), kBlock, 0, st>>>(lb, ncb, A.a_ptr, A.a_col, Vals<T>::a(A),
-                                                            C, S);
-    TB_HIP(hipGetLastError());
-    constexpr int R = 8;
-    const int64_t nrb = (la + R - 1) / R;
-    k_bb_sweep<T, R><<<(unsigned)(nrb * ncb), kBlock, 0, st>>>(la, lb, ncb, B.a_ptr, B.a_col,
-                                                                 Vals<T>::a(B), C, S);
-    TB_HIP(hipGetLastError());
-    k_ab_direct<T><<<(unsigned)(la * ncb), kBlock, 0, st>>>(lb, ncb, c.P, A.s_ptr, A.s_ent, B.s_ptr,
-                                                             B.s_ent, Vals<T>::V(c), C, S);
-    TB_HIP(hipGetLastError());
+    const int prec = sizeof(T) == 8 ? TBSCI_FP64 : TBSCI_FP32;
+    T *Ct = workspace<T>(c, 0);
+    T *St = workspace<T>(c, 1);
+
+    timing_mark(c, 0, prec, st);
+    if (terms & 1)
+        launch_row_sweep<T>(A, lb, C, S, false, st);  // sigma = A_a C
+    else
+        TB_HIP(hipMemsetAsync(S, 0, (size_t)(la * lb) * sizeof(T), st));
+    timing_mark(c, 1, prec, st);
+    if (terms & 2) {
+        launch_transpose<T, false>(la, lb, C, Ct, st);  // sigma += (A_b C^T)^T
+        launch_row_sweep<T>(B, la, Ct, St, false, st);
+        launch_transpose<T, true>(lb, la, St, S, st);
+    }
+    timing_mark(c, 2, prec, st);
+    const int ks = std::max((A.max_s + 3) / 4, 1);
+    const bool lds_row = ab_lds(lb, 4 * ks, c.P, sizeof(T), true).total <= kLdsMax;
+    if (!(terms & 4)) {
+    } else if (!launch_ab<T>(c, C, S, lds_row, st)) {
+        const int64_t ncb = (lb + kBlock - 1) / kBlock;
+        k_ab_direct<T><<<(unsigned)(la * ncb), kBlock, 0, st>>>(lb, ncb, c.P, A.s_ptr, A.s_ent,
+                                                                 B.s_ptr, B.s_ent, Vals<T>::V(c),
+                                                                 C, S);
+        TB_HIP(hipGetLastError());
+    }
+    timing_mark(c, 3, prec, st);
 }
 
 }  // namespace
 
-void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st) {
+void timing_mark(Ctx &c, int index, int precision, hipStream_t st) {
+    if (!c.timing) return;
+    if (index == 0) {
+        Ctx::TimedCall t{};
+        t.precision = precision;
+        for (auto &e : t.ev) TB_HIP(hipEventCreate(&e));
+        c.timed.push_back(t);
+    }
+    TB_HIP(hipEventRecord(c.timed.back().ev[index], st));
+}
+
+void timing_clear(Ctx &c) {
+    for (auto &t : c.timed)
+        for (auto &e : t.ev)
+            if (e) (void)hipEventDestroy(e);
+    c.timed.clear();
+}
+
+void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms) {
     if (precision == TBSCI_FP64)
-        sigma_impl<double>(c, (const double *)C, (double *)S, st);
+        sigma_impl<double>(c, (const double *)C, (double *)S, st, terms);
     else
-        sigma_impl<float>(c, (const float *)C, (float *)S, st);
+        sigma_impl<float>(c, (const float *)C, (float *)S, st, terms);
 }
 
 }  // namespace tbsci

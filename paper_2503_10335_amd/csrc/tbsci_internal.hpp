@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "../../include/tbsci.h"
 
@@ -69,7 +70,18 @@ struct Ctx {
     // sigma workspace (grown on demand)
     void *work = nullptr;
     size_t work_bytes = 0;
+    // per-kernel event timing (measurement only)
+    bool timing = false;
+    struct TimedCall {
+        int precision;
+        hipEvent_t ev[TBSCI_N_KERNELS + 1];
+    };
+    std::vector<TimedCall> timed;
 };
+
+// records an event on st if timing is on; index 0..TBSCI_N_KERNELS
+void timing_mark(Ctx &c, int index, int precision, hipStream_t st);
+void timing_clear(Ctx &c);
 
 extern thread_local std::string g_err;
 
@@ -103,7 +115,7 @@ void launch_full_diag(const Ctx &c, double *out, hipStream_t st);
 void launch_diag_argmin(const Ctx &c, double *part_val, int64_t *part_idx, int nblk, hipStream_t st);
 
 // ---- launchers (sigma_kernels.hip)
-void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st);
+void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms = 7);
 
 // ---- davidson.hip
 int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *C_out,

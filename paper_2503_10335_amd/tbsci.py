@@ -71,6 +71,7 @@ def load():
         "tbsci_destroy": (None, [P]),
         "tbsci_dims": (c_int, [P, P, P, P]),
         "tbsci_sigma": (c_int, [P, P, P, c_int, P]),
+        "tbsci_sigma_terms": (c_int, [P, P, P, c_int, c_int, P]),
         "tbsci_diag": (c_int, [P, P, P]),
         "tbsci_davidson_default_opts": (None, [P]),
         "tbsci_davidson": (c_int, [P, P, P, P, P, P]),
@@ -78,6 +79,8 @@ def load():
         "tbsci_lookup": (c_int, [P, c_int, P, i64, P, P]),
         "tbsci_list_size": (c_int, [P, c_int, c_int, P]),
         "tbsci_get_list": (c_int, [P, c_int, c_int, P, P, P]),
+        "tbsci_timing_enable": (c_int, [P, c_int]),
+        "tbsci_timing_read": (c_int, [P, c_int, c_int, P, P, P, P, P]),
         "tbsci_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -139,6 +142,12 @@ def tbsci_sigma(ctx, C, S, precision=TBSCI_FP64, stream=None):
                               int(precision), _stream(stream)))
 
 
+def tbsci_sigma_terms(ctx, C, S, precision=TBSCI_FP64, terms=7, stream=None):
+    _check(load().tbsci_sigma_terms(ctx, ctypes.c_void_p(C.data_ptr()),
+                                    ctypes.c_void_p(S.data_ptr()), int(precision), int(terms),
+                                    _stream(stream)))
+
+
 def tbsci_diag(ctx, D, stream=None):
     _check(load().tbsci_diag(ctx, ctypes.c_void_p(D.data_ptr()), _stream(stream)))
 
@@ -190,6 +199,24 @@ def tbsci_get_list(ctx, spin, kind, l):
     return ptr, ent[:n]
 
 
+TBSCI_N_KERNELS = 3
+
+
+def tbsci_timing_enable(ctx, enable=True):
+    _check(load().tbsci_timing_enable(ctx, 1 if enable else 0))
+
+
+def tbsci_timing_read(ctx, kernel, precision=TBSCI_FP64):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    fl, by = ctypes.c_double(), ctypes.c_double()
+    name = ctypes.c_char_p()
+    _check(load().tbsci_timing_read(ctx, int(kernel), int(precision), ctypes.byref(ms),
+                                    ctypes.byref(n), ctypes.byref(fl), ctypes.byref(by),
+                                    ctypes.byref(name)))
+    return dict(name=name.value.decode(), total_ms=ms.value, launches=n.value, flops=fl.value,
+                bytes=by.value)
+
+
 # ---------------------------------------------------------------- wrapper
 
 class Context:
@@ -234,6 +261,14 @@ class Context:
         elif out.dtype != dt or not out.is_contiguous() or out.numel() != self.n_det:
             raise ValueError("out must be a contiguous tensor like C")
         tbsci_sigma(self._ctx, C, out, precision, stream)
+        return out
+
+    def sigma_terms(self, C, terms, precision=TBSCI_FP64, stream=None):
+        dt = torch.float64 if precision == TBSCI_FP64 else torch.float32
+        if C.dtype != dt or not C.is_cuda or not C.is_contiguous() or C.numel() != self.n_det:
+            raise ValueError("C must be a contiguous device tensor of n_det elements")
+        out = torch.empty((self.l_alpha, self.l_beta), dtype=dt, device=C.device)
+        tbsci_sigma_terms(self._ctx, C, out, precision, terms, stream)
         return out
 
     def diag(self, stream=None):

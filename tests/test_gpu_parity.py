@@ -127,6 +127,34 @@ def test_sigma_fp64(env, name):
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["fci_m8", "rand_m8_3_4", "ranked_m11_indep", "empty_alpha",
+                                  "full_alpha"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sigma_terms_separately(env, name, prec):
+    """Each of the three terms against the oracle: A_a C and C A_b^T from the
+    oracle's dense same-spin matrices, the opposite-spin term as the rest."""
+    T, O, torch = env
+    p = PROBS[name]
+    ctx = T.Context.from_problem(p)
+    sp = O.Space.of(p)
+    C = W.random_vector(ctx.l_alpha, ctx.l_beta, seed=5)
+    full = sp.sigma(C)
+    ta = sp.same_spin_matrix(0) @ C
+    tb = C @ sp.same_spin_matrix(1).T
+    refs = {1: ta, 2: tb, 4: full - ta - tb, 7: full}
+    pr = T.TBSCI_FP64 if prec == "fp64" else T.TBSCI_FP32
+    Cd = torch.from_numpy(C).cuda()
+    if pr == T.TBSCI_FP32:
+        Cd = Cd.float()
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    scale = np.linalg.norm(full)
+    for mask, ref in refs.items():
+        got = ctx.sigma_terms(Cd, mask, precision=pr).double().cpu().numpy()
+        err = np.linalg.norm(got - ref) / scale
+        assert err <= tol, (mask, err)
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["fci_m8", "rand_m12_4_6", "ranked_m12", "one_by_one"])
 def test_sigma_fp32(env, name):
     T, O, torch = env
@@ -170,7 +198,7 @@ def test_davidson_fp64_vs_dense(env, name):
     if sp.n_det <= 6000:
         e_ref, _ = O.lowest_eigpair_dense(sp.dense_h())
     else:
-        res = O.davidson(sp.sigma, sp.diag(), tol=1e-10, n_max=12)
+        res = O.davidson(sp.sigma, sp.diag(), tol=1e-9, n_max=12)
         assert res["converged"]
         e_ref = res["energy"]
     info, X = ctx.davidson(tol_resid=1e-8, n_max=8)

@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (a kernel of known "
+                         "traffic for scaling profiler byte counters)")
+    ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 sigma leg")
     return ap.parse_args()
 
 
@@ -74,6 +78,13 @@ def main():
     print(f"# workload {args.workload}: l_alpha={ctx.l_alpha} l_beta={ctx.l_beta} "
           f"n_det={n_det} create {create_s:.3f}s", file=sys.stderr, flush=True)
 
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     C64 = torch.from_numpy(W.random_vector(ctx.l_alpha, ctx.l_beta, seed=7)).to(dev)
     S64 = torch.empty_like(C64)
     C32 = C64.float()
@@ -95,7 +106,8 @@ def main():
         return el, kernels
 
     el64, k64 = timed(C64, S64, T.TBSCI_FP64, args.steps, args.warmup)
-    el32, k32 = timed(C32, S32, T.TBSCI_FP32, args.steps, args.warmup)
+    el32, k32 = (1.0, None) if args.fp64_only else timed(C32, S32, T.TBSCI_FP32, args.steps,
+                                                          args.warmup)
     value = n_det * args.steps / el64
     print(f"# fp64 sigma {1e3 * el64 / args.steps:.3f} ms/step, fp32 "
           f"{1e3 * el32 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
@@ -111,7 +123,7 @@ def main():
         return out
 
     kt64 = kernel_table(k64, T.TBSCI_FP64)
-    kt32 = kernel_table(k32, T.TBSCI_FP32)
+    kt32 = kernel_table(k32, T.TBSCI_FP32) if k32 else None
     dom = max(k64, key=lambda k: k["total_ms"])
     dom_avg = dom["total_ms"] / dom["launches"] * 1e-3
     achieved = dom["flops"] / dom_avg / 1e12

@@ -70,8 +70,8 @@ T *dalloc(size_t n) {
 }
 
 void free_spin(Spin &s) {
-    void *ptrs[] = {s.str,  s.keys,  s.pos,   s.s_ptr,   s.s_ent, s.d_ptr, s.d_ent,
-                    s.a_ptr, s.a_col, s.a_val, s.a_val32, s.dsame, s.jocc};
+    void *ptrs[] = {s.str,   s.keys,  s.pos,     s.s_ptr, s.s_ent, s.d_ptr, s.d_ent, s.a_ptr,
+                    s.a_col, s.a_val, s.a_val32, s.dsame, s.jocc,  s.g_ent, s.g_off};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     s = Spin{};

@@ -317,6 +317,29 @@ __global__ __launch_bounds__(kBlock) void k_same_spin(
     }
 }
 
+// Regroup each singles row by (MFMA tile t = pair / 16, lane group
+// g = (pair % 16) & 3) of the folded pair index: a counting sort per row, one
+// thread per row, list order kept inside a group.  Group key = 4 t + g.
+__global__ void k_group_by_tile(const int64_t *__restrict__ s_ptr, const Ent *__restrict__ s_ent,
+                                int64_t l, int ngroup, Ent *__restrict__ g_ent,
+                                int32_t *__restrict__ g_off) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= l) return;
+    const int64_t b = s_ptr[row], e = s_ptr[row + 1];
+    int32_t *off = g_off + row * (ngroup + 1);
+    auto key = [](uint32_t o) {
+        const int pair = (int)(o >> 16);
+        return 4 * (pair >> 4) + ((pair & 15) & 3);
+    };
+    for (int t = 0; t <= ngroup; ++t) off[t] = 0;
+    for (int64_t i = b; i < e; ++i) off[key(s_ent[i].o) + 1]++;
+    for (int t = 0; t < ngroup; ++t) off[t + 1] += off[t];
+    for (int t = ngroup; t > 0; --t) off[t] = off[t - 1];  // off[t + 1] = start of group t
+    off[0] = 0;
+    for (int64_t i = b; i < e; ++i) g_ent[b + off[key(s_ent[i].o) + 1]++] = s_ent[i];
+    // off[t + 1] advanced to the end of group t = start of group t + 1
+}
+
 // H_KK = d_alpha(I) + d_beta(I') + sum_{p in I} jocc_beta[I'][p]
 __global__ void k_full_diag(const uint64_t *__restrict__ astr, int64_t la, int64_t lb, int M,
                             const double *__restrict__ da, const double *__restrict__ db,
@@ -410,6 +433,15 @@ void build_spin(Ctx &c, Spin &s, const uint64_t *host_str, hipStream_t st) {
     s.s_ent = dalloc<Ent>(s.n_s);
     k_singles<true><<<wblocks, kBlock, 0, st>>>(s.str, l, M, s.keys, s.pos, nullptr, s.s_ptr, s.s_ent);
     TB_HIP(hipGetLastError());
+    // singles regrouped by MFMA pair tile (the opposite-spin scatter reads these)
+    {
+        const int ngroup = 4 * ((c.P + 15) / 16);
+        s.g_ent = dalloc<Ent>(s.n_s);
+        s.g_off = dalloc<int32_t>((size_t)l * (ngroup + 1));
+        k_group_by_tile<<<blocks_for(l, 128), 128, 0, st>>>(s.s_ptr, s.s_ent, l, ngroup, s.g_ent,
+                                                             s.g_off);
+        TB_HIP(hipGetLastError());
+    }
     // doubles
     s.d_ptr = dalloc<int64_t>(l + 1);
     k_doubles<false><<<wblocks, kBlock, 0, st>>>(s.str, l, M, s.keys, s.pos, cnt, nullptr, nullptr);

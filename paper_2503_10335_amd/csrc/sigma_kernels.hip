@@ -16,10 +16,12 @@
 //   opposite spin : per output alpha row, gather the rows of C linked by
 //                   alpha single excitations, multiply by the folded (pq|rs)
 //                   block on MFMA, scatter through the beta single lists
-//                   into the output row held in LDS (LDS atomics);
+//                   into the output row (LDS atomics when it fits in LDS);
 //   alpha sweep   : sparse rows of A_a times rows of C, one XCD per column
 //                   panel so each XCD's L2 holds its panel of C;
 //   beta sweep    : the same kernel on C^T, then a transpose-add.
+#include <type_traits>
+
 #include "tbsci_internal.hpp"
 
 namespace tbsci {
@@ -149,16 +151,58 @@ struct Mfma<float> {
     }
 };
 
-constexpr int kTW = 32;         // source beta columns per tile (2 MFMA N-subtiles)
+// One block per output alpha row I; wave w owns MFMA M-tile w, i.e. 16
+// folded pairs rs, so blockDim = 64 * ceil(P / 16).  Per tile of kTW beta
+// columns:
+//
+//   X[k][c]  = C[J_k][c]                     (gathered, k over the alpha links
+//                                              of I; double-buffered in LDS)
+//   Y[rs][c] = sum_k s_k V[pq_k][rs] X[k][c]  (MFMA; A fragments in registers)
+//   row[I']  += s * Y[pair][J']  for every link (I', pair, s) of J' in the
+//               beta single lists (symmetric: the links of J' are the
+//               sources of I')
+//
+// Y never leaves the accumulators: the A rows are ordered so that register r
+// of a lane in lane group g holds pair 16 w + 4 r + g of its column, and the
+// links are grouped by (tile, g), so each lane reads just its own links.
+// The next tile's X elements and link offsets are loaded into registers
+// while the current tile is multiplied; one barrier per tile.
+//
+// ROW selects where the output row accumulates: an FP64 row in LDS (FP64
+// LDS atomics, also for FP32 sigma: on gfx950 they are several times faster
+// than FP32 LDS atomics, and the row is rounded once at the end), a row of
+// type T in LDS, or sigma itself through global atomics.
+#ifndef TB_AB_TW
+#define TB_AB_TW 32
+#endif
+constexpr int kTW = TB_AB_TW;   // beta columns per tile (16-column MFMA N-subtiles)
 constexpr int kNS = kTW / 16;
-constexpr int kXS = kTW + 1;    // LDS row stride of the X and Y tiles
+constexpr int kXS = kTW + 1;    // LDS row stride of an X tile
+constexpr int kXPT = kTW / 4;   // X-tile elements per thread
+
+template <typename T>
+__device__ __forceinline__ int a_row_pair(int m);  // pair (within the tile) of A row m
+template <>
+__device__ __forceinline__ int a_row_pair<double>(int m) {
+    return m;  // FP64 accumulator: row m = 4 r + g
+}
+template <>
+__device__ __forceinline__ int a_row_pair<float>(int m) {
+    return 4 * (m & 3) + (m >> 2);  // FP32 accumulator: row m = 4 g + r
+}
+
+template <typename V4>
+__device__ __forceinline__ auto pick4(const V4 &v, int r) {
+    return r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
+}
+
+enum { kRowF64 = 0, kRowT = 1, kRowGlobal = 2 };
 
 struct AbLds {
-    size_t row, aj, bp, x, y, total;
+    size_t row, aj, x, total;
 };
 
-// LDS layout of k_ab_gemm (bytes)
-inline AbLds ab_lds(int64_t lb, int kmax, int P, size_t sz, bool lds_row) {
+inline AbLds ab_lds(int64_t lb, int kmax, size_t sz, size_t row_sz) {
     AbLds L{};
     size_t o = 0;
     auto take = [&](size_t n) {
@@ -166,63 +210,53 @@ inline AbLds ab_lds(int64_t lb, int kmax, int P, size_t sz, bool lds_row) {
         o += (n + 15) & ~size_t(15);
         return at;
     };
-    L.row = take(lds_row ? (size_t)lb * sz : 0);
+    L.row = take((size_t)lb * row_sz);
     L.aj = take((size_t)kmax * 4);
-    L.bp = take((kTW + 1) * 8);
-    L.x = take((size_t)kmax * kXS * sz);
-    L.y = take((size_t)P * kXS * sz);
+    L.x = take(2 * (size_t)kmax * kXS * sz);
     L.total = o;
     return L;
 }
 
-// One block per output alpha row I; wave w owns MFMA M-tile w (pairs
-// rs = 16w .. 16w+15), so blockDim = 64 * ceil(P/16).
-//
-//   X[k][c]  = C[J_k][c]                     (gather, k over the alpha links of I)
-//   Y[rs][c] = sum_k s_k V[pq_k][rs] X[k][c]  (MFMA, K = links, M = folded pairs)
-//   row[I']  += s * Y[pair][J']  for every link (I', pair, s) of J' in the
-//               beta single lists (the lists are symmetric: the links of J'
-//               are the sources of I')
-//
-// KS = maximum number of 4-deep MFMA k-steps (links padded to 4 * KS).
-// With LDS_ROW the output row lives in LDS and is added to sigma at the
-// end; otherwise the scatter adds into sigma with global atomics.
-template <typename T, int KS, bool LDS_ROW>
-__global__ __launch_bounds__(1024) void k_ab_gemm(int64_t lb, int P, AbLds L,
+template <typename T, int KS, int ROW, int BOUND>
+__global__ __launch_bounds__(BOUND) void k_ab_tile(int64_t lb, int P, int nmt, AbLds L,
                                                   const int64_t *__restrict__ sa_ptr,
                                                   const Ent *__restrict__ sa_ent,
                                                   const int64_t *__restrict__ sb_ptr,
-                                                  const Ent *__restrict__ sb_ent,
+                                                  const Ent *__restrict__ sb_grp,
+                                                  const int32_t *__restrict__ sb_off,
                                                   const T *__restrict__ V, const T *__restrict__ C,
                                                   T *__restrict__ S) {
     using M = Mfma<T>;
+    using R = typename std::conditional<ROW == kRowF64, double, T>::type;
+    constexpr bool LDS_ROW = ROW != kRowGlobal;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *row = (T *)(smem + L.row);
+    R *row = (R *)(smem + L.row);
     int32_t *aj = (int32_t *)(smem + L.aj);
-    int64_t *bp = (int64_t *)(smem + L.bp);
-    T *xt = (T *)(smem + L.x);
-    T *yt = (T *)(smem + L.y);
+    T *xbuf = (T *)(smem + L.x);
 
     const int64_t I = blockIdx.x;
-    const int nthr = blockDim.x;
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, cl = lane & 15;
     const int64_t a0 = sa_ptr[I];
     const int K = (int)(sa_ptr[I + 1] - a0);
     const int nks = (K + 3) >> 2, Kp = nks * 4;
+    const int nx = Kp * kTW;
+    const int ng = 4 * nmt;
+    const int key = 4 * wave + g;  // this lane's link group
 
     if (LDS_ROW)
-        for (int64_t i = tid; i < lb; i += nthr) row[i] = T(0);
+        for (int64_t i = tid; i < lb; i += nthr) row[i] = R(0);
     for (int k = tid; k < Kp; k += nthr) aj[k] = k < K ? sa_ent[a0 + k].j : -1;
 
-    // A fragments of this wave's M-tile: lane holds U[k = 4ks + lane/16][m = lane%16]
+    // A fragments: lane holds U[k = 4 ks + g][row cl] of this wave's M-tile
     T ua[KS];
     {
-        const int m = wave * 16 + (lane & 15);
+        const int m = wave * 16 + a_row_pair<T>(cl);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             T a = T(0);
-            const int k = 4 * ks + (lane >> 4);
+            const int k = 4 * ks + g;
             if (ks < nks && k < K && m < P) {
                 const Ent e = sa_ent[a0 + k];
                 const T v = V[(int64_t)(e.o >> 16) * P + m];
@@ -233,65 +267,99 @@ __global__ __launch_bounds__(1024) void k_ab_gemm(int64_t lb, int P, AbLds L,
     }
     __syncthreads();
 
-    const int64_t ntile = (lb + kTW - 1) / kTW;
-    for (int64_t t = 0; t < ntile; ++t) {
-        const int64_t j0 = t * kTW;
-        // gather X tile and the tile's beta list pointers
-        for (int i = tid; i < Kp * kTW; i += nthr) {
-            const int k = i / kTW, cc = i - k * kTW;
-            const int32_t J = aj[k];
+    T xr[kXPT];
+    auto load_x = [&](int64_t j0) {
+#pragma unroll
+        for (int u = 0; u < kXPT; ++u) {
+            const int i = tid + u * nthr;
             T v = T(0);
-            if (J >= 0 && j0 + cc < lb) v = C[(int64_t)J * lb + j0 + cc];
-            xt[k * kXS + cc] = v;
+            if (i < nx) {
+                const int k = i / kTW, cc = i - k * kTW;
+                const int32_t J = aj[k];
+                if (J >= 0 && j0 + cc < lb) v = C[(int64_t)J * lb + j0 + cc];
+            }
+            xr[u] = v;
         }
-        for (int i = tid; i <= kTW; i += nthr) bp[i] = sb_ptr[j0 + i < lb ? j0 + i : lb];
-        __syncthreads();
-        // MFMA: Y tile rows of this wave's M-tile
-        if (wave * 16 < P) {
-            typename M::acc_t acc[kNS];
+    };
+    auto store_x = [&](T *xt) {
 #pragma unroll
-            for (int ns = 0; ns < kNS; ++ns) acc[ns] = typename M::acc_t{0, 0, 0, 0};
+        for (int u = 0; u < kXPT; ++u) {
+            const int i = tid + u * nthr;
+            if (i < nx) {
+                const int k = i / kTW, cc = i - k * kTW;
+                xt[k * kXS + cc] = xr[u];
+            }
+        }
+    };
+    // link ranges of this lane's group for its columns of a tile
+    int64_t lb0[kNS];
+    int32_t ln0[kNS];
+    auto load_off = [&](int64_t j0) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
+        for (int ns = 0; ns < kNS; ++ns) {
+            const int64_t col = j0 + ns * 16 + cl;
+            lb0[ns] = 0;
+            ln0[ns] = 0;
+            if (wave < nmt && col < lb) {
+                const int32_t *off = sb_off + col * (ng + 1) + key;
+                const int32_t o0 = off[0];
+                lb0[ns] = sb_ptr[col] + o0;
+                ln0[ns] = off[1] - o0;
+            }
+        }
+    };
+
+    const int64_t ntile = (lb + kTW - 1) / kTW;
+    load_x(0);
+    store_x(xbuf);
+    load_off(0);
+    __syncthreads();
+    for (int64_t t = 0; t < ntile; ++t) {
+        T *xt = xbuf + (size_t)(t & 1) * Kp * kXS;
+        const int64_t j0 = t * kTW;
+        // this tile's link ranges (offsets arrived during the previous tile)
+        int64_t eb[kNS];
+        int32_t en[kNS];
+#pragma unroll
+        for (int ns = 0; ns < kNS; ++ns) {
+            eb[ns] = lb0[ns];
+            en[ns] = ln0[ns];
+        }
+        if (t + 1 < ntile) {
+            load_x(j0 + kTW);
+            load_off(j0 + kTW);
+        }
+        typename M::acc_t acc[kNS];
+#pragma unroll
+        for (int ns = 0; ns < kNS; ++ns) acc[ns] = typename M::acc_t{0, 0, 0, 0};
+        if (wave < nmt) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
                 if (ks < nks) {
-                    const int k = 4 * ks + (lane >> 4);
+                    const int k = 4 * ks + g;
 #pragma unroll
                     for (int ns = 0; ns < kNS; ++ns)
-                        acc[ns] = M::mma(ua[ks], xt[k * kXS + ns * 16 + (lane & 15)], acc[ns]);
-                }
-            }
-#pragma unroll
-            for (int ns = 0; ns < kNS; ++ns)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int m = wave * 16 + M::row(lane, r);
-                    if (m < P) yt[m * kXS + ns * 16 + (lane & 15)] = acc[ns][r];
+                        acc[ns] = M::mma(ua[ks], xt[k * kXS + ns * 16 + cl], acc[ns]);
                 }
         }
-        __syncthreads();
-        // scatter through the beta links of the tile's source columns
-        const int64_t e0 = bp[0], e1 = bp[kTW];
-        for (int64_t e = e0 + tid; e < e1; e += nthr) {
-            int lo = 0, hi = kTW;  // column: bp[lo] <= e < bp[lo+1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (bp[mid] <= e)
-                    lo = mid;
+        // scatter this lane's links: register r holds pair 16 w + 4 r + g
+#pragma unroll
+        for (int ns = 0; ns < kNS; ++ns) {
+            for (int32_t x = 0; x < en[ns]; ++x) {
+                const Ent e = sb_grp[eb[ns] + x];
+                T v = pick4(acc[ns], (int)(((e.o >> 16) & 15) >> 2));
+                if ((e.o >> 12) & 1u) v = -v;
+                if (LDS_ROW)
+                    atomicAdd(&row[e.j], (R)v);
                 else
-                    hi = mid;
+                    atomicAdd(&S[I * lb + e.j], v);
             }
-            const Ent eb = sb_ent[e];
-            T v = yt[(int)(eb.o >> 16) * kXS + lo];
-            if ((eb.o >> 12) & 1u) v = -v;
-            if (LDS_ROW)
-                atomicAdd(&row[eb.j], v);
-            else
-                atomicAdd(&S[I * lb + eb.j], v);
         }
+        if (t + 1 < ntile) store_x(xbuf + (size_t)((t + 1) & 1) * Kp * kXS);
         __syncthreads();
     }
     if (LDS_ROW)
-        for (int64_t i = tid; i < lb; i += nthr) S[I * lb + i] += row[i];
+        for (int64_t i = tid; i < lb; i += nthr) S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
 }
 
 // ---------------------------------------------------------------- driver
@@ -332,39 +400,59 @@ void launch_transpose(int64_t R, int64_t Cn, const T *in, T *out, hipStream_t st
     TB_HIP(hipGetLastError());
 }
 
-template <typename T, int KS>
-void launch_ab_ks(Ctx &c, const T *C, T *S, bool lds_row, hipStream_t st) {
-    const Spin &A = c.sp[0], &B = c.sp[1];
-    const int P = c.P;
-    const int nw = (P + 15) / 16;
-    const AbLds L = ab_lds(B.l, 4 * KS, P, sizeof(T), lds_row);
-    if (lds_row) {
-        auto f = k_ab_gemm<T, KS, true>;
-        TB_HIP(hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)L.total));
-        f<<<(unsigned)A.l, 64 * nw, L.total, st>>>(B.l, P, L, A.s_ptr, A.s_ent, B.s_ptr, B.s_ent,
-                                                   Vals<T>::V(c), C, S);
-    } else {
-        auto f = k_ab_gemm<T, KS, false>;
-        TB_HIP(hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)L.total));
-        f<<<(unsigned)A.l, 64 * nw, L.total, st>>>(B.l, P, L, A.s_ptr, A.s_ent, B.s_ptr, B.s_ent,
-                                                   Vals<T>::V(c), C, S);
-    }
-    TB_HIP(hipGetLastError());
+// raise a kernel's dynamic LDS limit once per context and kernel
+void allow_lds(Ctx &c, const void *f, size_t bytes) {
+    for (auto &e : c.lds_set)
+        if (e.first == f && e.second >= bytes) return;
+    TB_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    c.lds_set.emplace_back(f, bytes);
 }
 
 constexpr size_t kLdsMax = 160 * 1024;
 
+template <typename T, int KS, int BOUND>
+void launch_ab_kb(Ctx &c, const T *C, T *S, hipStream_t st) {
+    const Spin &A = c.sp[0], &B = c.sp[1];
+    const int P = c.P, nmt = (P + 15) / 16;
+    int row = kRowGlobal;
+    AbLds L = ab_lds(B.l, 4 * KS, sizeof(T), 0);
+    if (ab_lds(B.l, 4 * KS, sizeof(T), 8).total <= kLdsMax) {
+        row = kRowF64;
+        L = ab_lds(B.l, 4 * KS, sizeof(T), 8);
+    } else if (sizeof(T) < 8 && ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T)).total <= kLdsMax) {
+        row = kRowT;
+        L = ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T));
+    }
+    auto f = row == kRowF64 ? k_ab_tile<T, KS, kRowF64, BOUND>
+             : row == kRowT ? k_ab_tile<T, KS, kRowT, BOUND>
+                            : k_ab_tile<T, KS, kRowGlobal, BOUND>;
+    if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
+    f<<<(unsigned)A.l, 64 * nmt, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
+                                                B.g_ent, B.g_off, Vals<T>::V(c), C, S);
+    TB_HIP(hipGetLastError());
+}
+
+// a tighter launch bound leaves more registers per lane (no spills)
+template <typename T, int KS>
+void launch_ab_ks(Ctx &c, const T *C, T *S, hipStream_t st) {
+    if ((c.P + 15) / 16 <= 10)
+        launch_ab_kb<T, KS, 640>(c, C, S, st);
+    else
+        launch_ab_kb<T, KS, 1024>(c, C, S, st);
+}
+
 // opposite-spin term; returns false if this shape needs the direct kernel
 template <typename T>
-bool launch_ab(Ctx &c, const T *C, T *S, bool lds_row, hipStream_t st) {
-    const int ks = (c.sp[0].max_s + 3) / 4;
-    if (c.P > 256 || ks > 32) return false;
-#define TB_KS(n)                                        \
-    if (ks <= n) {                                      \
-        launch_ab_ks<T, n>(c, C, S, lds_row, st);       \
-        return true;                                    \
+bool launch_ab(Ctx &c, const T *C, T *S, hipStream_t st) {
+    const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
+    const int nmt = (c.P + 15) / 16;
+    if (ks > 32 || nmt > 16) return false;
+    // every X-tile element needs a prefetch register
+    if (4 * ks * kTW > kXPT * 64 * nmt) return false;
+#define TB_KS(n)                                \
+    if (ks <= n) {                              \
+        launch_ab_ks<T, n>(c, C, S, st);        \
+        return true;                            \
     }
     TB_KS(4) TB_KS(8) TB_KS(12) TB_KS(16) TB_KS(20) TB_KS(24) TB_KS(28) TB_KS(32)
 #undef TB_KS
@@ -421,10 +509,8 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms) {
         launch_transpose<T, true>(lb, la, St, S, st);
     }
     timing_mark(c, 2, prec, st);
-    const int ks = std::max((A.max_s + 3) / 4, 1);
-    const bool lds_row = ab_lds(lb, 4 * ks, c.P, sizeof(T), true).total <= kLdsMax;
     if (!(terms & 4)) {
-    } else if (!launch_ab<T>(c, C, S, lds_row, st)) {
+    } else if (!launch_ab<T>(c, C, S, st)) {
         const int64_t ncb = (lb + kBlock - 1) / kBlock;
         k_ab_direct<T><<<(unsigned)(la * ncb), kBlock, 0, st>>>(lb, ncb, c.P, A.s_ptr, A.s_ent,
                                                                  B.s_ptr, B.s_ent, Vals<T>::V(c),

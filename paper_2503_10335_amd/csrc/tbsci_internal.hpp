@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/tbsci.h"
@@ -58,6 +59,11 @@ struct Spin {
     double *jocc = nullptr;    // [l][M]: sum_{r in I} (pp|rr) for each p
     int64_t n_s = 0, n_d = 0, n_a = 0;
     int max_s = 0;             // longest singles row
+    // the singles rows regrouped by (16-pair MFMA tile t, lane group g) of
+    // their folded pair index (same row pointers as s_ptr);
+    // g_off[row * (4 ntile + 1) + 4 t + g] is the start of that group in the row
+    Ent *g_ent = nullptr;
+    int32_t *g_off = nullptr;
 };
 
 struct Ctx {
@@ -77,6 +83,8 @@ struct Ctx {
         hipEvent_t ev[TBSCI_N_KERNELS + 1];
     };
     std::vector<TimedCall> timed;
+    // kernels whose dynamic LDS limit has been raised (kernel, bytes)
+    std::vector<std::pair<const void *, size_t>> lds_set;
 };
 
 // records an event on st if timing is on; index 0..TBSCI_N_KERNELS

@@ -17,7 +17,8 @@ import numpy as np
 import torch  # loads the HIP runtime the library binds to (same soname)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtbsci.so")
+# TBSCI_LIB may point at another build of the same library (same ABI)
+LIB_PATH = os.environ.get("TBSCI_LIB") or os.path.join(_HERE, "libtbsci.so")
 
 TBSCI_OK = 0
 TBSCI_PENDING = 1

@@ -32,6 +32,119 @@ PEAK = {  # MI355X published peaks
 }
 
 
+PROFILE = os.path.join(ROOT, "profiles", "sigma_kernels_sel_m16.txt")
+SIGMA_SRC = os.path.join(ROOT, "paper_2503_10335_amd", "csrc", "sigma_kernels.hip")
+KERNEL_LABEL = {  # kernel-name prefix in the profiler -> (timing name, precision)
+    "k_ab_tile<double": ("opposite_spin", "fp64"),
+    "k_ab_tile<float": ("opposite_spin", "fp32"),
+    "k_ab_direct<double": ("opposite_spin", "fp64"),
+    "k_ab_direct<float": ("opposite_spin", "fp32"),
+}
+COPY_BYTES = 256 * 1024 * 1024  # the --copy-calibration copy
+
+
+def source_hash() -> str:
+    """Hash of the opposite-spin kernel's device code and launch code."""
+    import hashlib
+    text = open(SIGMA_SRC).read()
+    parts = []
+    for a, b in (("// ---------------------------------------------------------- opposite spin",
+                  "// ---------------------------------------------------------------- driver"),
+                 ("template <typename T, int KS, int BOUND>\nvoid launch_ab_kb",
+                  "// Opposite-spin term, direct double sum")):
+        i, j = text.find(a), text.find(b)
+        if i < 0 or j < i:
+            return "unknown"
+        parts.append(text[i:j])
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    import re
+    name = name.replace("tbsci::(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", name).strip()
+
+
+def summarize(trace_dir, fetch_dir, write_dir, out, commands):
+    """Write a short text summary of three rocprofv3 csv runs (kernel trace,
+    FETCH_SIZE pass, WRITE_SIZE pass) of this benchmark, including the HBM
+    bytes per launch of the opposite-spin kernel scaled by the copy kernel."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def one(pattern):
+        got = glob.glob(os.path.join(pattern))
+        if len(got) != 1:
+            raise SystemExit(f"expected one file for {pattern}, found {got}")
+        return got[0]
+
+    stats = list(csv.DictReader(open(one(os.path.join(trace_dir, "*kernel_stats.csv")))))
+    ctr = {}
+    for tag, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        agg = defaultdict(list)
+        for r in csv.DictReader(open(one(os.path.join(d, "*counter_collection.csv")))):
+            if r["Counter_Name"] == tag:
+                agg[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        ctr[tag] = agg
+    # the calibration copy is the largest copyBuffer dispatch
+    copy_f = max(ctr["FETCH_SIZE"]["__amd_rocclr_copyBuffer"]) * 1024.0
+    copy_w = max(ctr["WRITE_SIZE"]["__amd_rocclr_copyBuffer"]) * 1024.0
+    kf, kw = COPY_BYTES / copy_f, COPY_BYTES / copy_w
+    lines = ["# rocprofv3 summary: sigma kernels, selected TPB space M=16, N=8,",
+             "# 3000 x 3000 strings (9.0e6 determinants), FP64 and FP32 sigma builds",
+             "# commands (run from the repository root):"]
+    lines += [f"#   {c}" for c in commands]
+    lines.append(f"#   python3 bench.py --summarize {trace_dir} {fetch_dir} {write_dir} "
+                 f"--summary-out {os.path.relpath(out, ROOT)} (with the commands above "
+                 f"as --command arguments)")
+    lines += [f"source_sha256 {source_hash()}",
+              f"copy_calibration bytes {COPY_BYTES} fetch_counter_bytes {copy_f:.0f} "
+              f"write_counter_bytes {copy_w:.0f} fetch_factor {kf:.4f} write_factor {kw:.4f}",
+              "", "kernel-trace stats (top kernels by total time)",
+              f"{'kernel':34s} {'calls':>5s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    for r in stats[:12]:
+        lines.append(f"{short_name(r['Name'])[:34]:34s} {int(r['Calls']):5d} "
+                     f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['MinNs']) / 1e3:10.1f} "
+                     f"{float(r['MaxNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}")
+    lines += ["", "HBM bytes per dispatch (counter mean x calibration factor)",
+              f"{'kernel':34s} {'n':>3s} {'fetch_MB':>10s} {'write_MB':>10s}"]
+    traffic = {}
+    for k, v in ctr["FETCH_SIZE"].items():
+        if k.startswith("at::") or k.startswith("__amd"):
+            continue
+        w = ctr["WRITE_SIZE"].get(k, [0.0])
+        fb = sum(v) / len(v) * 1024.0 * kf
+        wb = sum(w) / len(w) * 1024.0 * kw
+        lines.append(f"{k[:34]:34s} {len(v):3d} {fb / 1e6:10.2f} {wb / 1e6:10.2f}")
+        for pre, (label, prec) in KERNEL_LABEL.items():
+            if k.startswith(pre):
+                traffic[(label, prec)] = fb + wb
+    lines.append("")
+    for (label, prec), b in sorted(traffic.items()):
+        lines.append(f"traffic {label} {prec} {b:.0f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def measured_traffic(label: str, prec: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernel source changed since it was taken."""
+    try:
+        text = open(PROFILE).read().splitlines()
+    except OSError:
+        return None
+    rec = dict(l.split(None, 1) for l in text if l.startswith("source_sha256 "))
+    if rec.get("source_sha256", "").strip() != source_hash():
+        return None
+    for l in text:
+        f = l.split()
+        if len(f) == 4 and f[0] == "traffic" and f[1] == label and f[2] == prec:
+            return float(f[3])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,11 +159,20 @@ def parse():
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic for scaling profiler byte counters)")
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 sigma leg")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="summarize three rocprofv3 csv runs of this benchmark into "
+                         "the profile summary and exit (no GPU)")
+    ap.add_argument("--summary-out", default=PROFILE)
+    ap.add_argument("--command", action="append", default=[],
+                    help="command line recorded in the summary (repeatable)")
     return ap.parse_args()
 
 
 def main():
     args = parse()
+    if args.summarize:
+        summarize(*args.summarize, args.summary_out, args.command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only (one process holds the whole CI "
@@ -124,20 +246,31 @@ def main():
 
     kt64 = kernel_table(k64, T.TBSCI_FP64)
     kt32 = kernel_table(k32, T.TBSCI_FP32) if k32 else None
+    # dominant kernel: the opposite-spin term, a dense contraction on FP64
+    # MFMA.  achieved = algorithmic flops of the direct double sum
+    # (2 n_s_alpha n_s_beta) over the event-timed average launch; the flops
+    # the padded MFMA tiles execute are reported beside it.
     dom = max(k64, key=lambda k: k["total_ms"])
     dom_avg = dom["total_ms"] / dom["launches"] * 1e-3
     achieved = dom["flops"] / dom_avg / 1e12
     roofline = {
         "kernel": dom["name"],
-        "bound": "alu",
+        "bound": "mfma" if dom["name"] == "opposite_spin" else "alu",
         "achieved": achieved,
         "peak": PEAK["fp64_tflops"],
         "unit": "TFLOP/s",
         "frac": achieved / PEAK["fp64_tflops"],
-        "traffic": None,
+        "traffic": measured_traffic(dom["name"], "fp64"),
         "avg_launch_ms": dom_avg * 1e3,
         "flops_per_launch": dom["flops"],
     }
+    if dom["name"] == "opposite_spin":
+        ex = ctx.mfma_flops(T.TBSCI_FP64)
+        roofline["executed_mfma_flops_per_launch"] = ex
+        roofline["executed_mfma_tflops"] = ex / dom_avg / 1e12
+        roofline["executed_frac"] = ex / dom_avg / 1e12 / PEAK["fp64_tflops"]
+    if roofline["traffic"] is not None:
+        roofline["traffic_gbs"] = roofline["traffic"] / dom_avg / 1e9
 
     result = {
         "metric": "H·C dets/s; Davidson time to 1e-6 Eh, FP32-MFMA vs FP64; p50/p99 solve latency",

@@ -240,6 +240,17 @@ int tbsci_timing_enable(tbsci_ctx *ctx, int enable);
 int tbsci_timing_read(tbsci_ctx *ctx, int kernel, int precision, double *total_ms,
                       int64_t *launches, double *flops, double *bytes, const char **name);
 
+/*
+ * flops = floating-point operations one launch of kernel `kernel` executes
+ * (for the MFMA opposite-spin kernel: the padded matrix tiles, i.e. the
+ * alpha link count of every row rounded up to a multiple of 4, times the
+ * (pq|rs) pairs rounded up to a multiple of 16, times the beta strings
+ * rounded up to the column-tile width, times 2; for the other kernels the
+ * same as the algorithmic count).  Returns TBSCI_E_INVAL for a bad index,
+ * precision or a NULL flops.
+ */
+int tbsci_timing_executed_flops(tbsci_ctx *ctx, int kernel, int precision, double *flops);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *tbsci_last_error(void);
 

@@ -14,7 +14,7 @@ SOURCES = ["api.hip", "index_kernels.hip", "sigma_kernels.hip", "davidson.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 vector ops are disabled on purpose
+    # no packed FP32 vector ops: some of their forms have given wrong results on this part
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",  # hardware float atomics (LDS and global adds)
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",

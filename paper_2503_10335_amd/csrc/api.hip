@@ -387,4 +387,16 @@ int tbsci_timing_read(tbsci_ctx *ctx, int kernel, int precision, double *total_m
     });
 }
 
+int tbsci_timing_executed_flops(tbsci_ctx *ctx, int kernel, int precision, double *flops) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        if (kernel < 0 || kernel >= TBSCI_N_KERNELS) throw Error(TBSCI_E_INVAL, "no such kernel");
+        if (precision != TBSCI_FP64 && precision != TBSCI_FP32)
+            throw Error(TBSCI_E_INVAL, "precision must be TBSCI_FP64 or TBSCI_FP32");
+        if (!flops) throw Error(TBSCI_E_INVAL, "flops is NULL");
+        *flops = executed_flops(*ctx_of(ctx), kernel, precision);
+        return TBSCI_OK;
+    });
+}
+
 }  // extern "C"

@@ -397,15 +397,19 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
                     fp32 ? "fp32" : "fp64", theta, rn);
 
         if (fp32) {
-            // the FP32 phase ends at fp32_switch_resid, or when the residual has
-            // not improved by 2% for 20 sigma builds (FP32 rounding floor)
+            // The FP32 phase ends at fp32_switch_resid, or when the residual
+            // has stopped improving close to the FP32 rounding floor of the
+            // sigma build (taken as 2e-6 |theta|); a plateau well above that
+            // floor is slow convergence, which FP64 would not cure.
             if (rn < 0.98 * best_rn) {
                 best_rn = rn;
                 since_best = 0;
             } else {
                 ++since_best;
             }
-            if (rn <= o.fp32_switch_resid || since_best >= 20 || info.iters >= o.max_iter / 2) {
+            const bool at_floor = rn < 10.0 * 2e-6 * std::fabs(theta);
+            if (rn <= o.fp32_switch_resid || (since_best >= 20 && at_floor) ||
+                info.iters >= o.max_iter / 2) {
                 // correction phase: restart from the Ritz vector with FP64 sigma builds
                 fp32 = false;
                 TB_HIP(hipMemcpyAsync(V[0], X, n * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -20,6 +20,7 @@
 //   alpha sweep   : sparse rows of A_a times rows of C, one XCD per column
 //                   panel so each XCD's L2 holds its panel of C;
 //   beta sweep    : the same kernel on C^T, then a transpose-add.
+#include <vector>
 #include <type_traits>
 
 #include "tbsci_internal.hpp"
@@ -545,6 +546,27 @@ void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st,
         sigma_impl<double>(c, (const double *)C, (double *)S, st, terms);
     else
         sigma_impl<float>(c, (const float *)C, (float *)S, st, terms);
+}
+
+// Floating-point operations one launch of kernel `kernel` executes: for the
+// MFMA opposite-spin kernel the padded tiles (K rounded up to the 4-deep
+// k-step, pairs to 16-row M-tiles, beta columns to kTW-wide tiles); for
+// the sweeps and the direct fallback the multiply-adds of their sums.
+double executed_flops(Ctx &c, int kernel, int precision) {
+    const Spin &A = c.sp[0], &B = c.sp[1];
+    if (kernel == 0) return 2.0 * (double)A.n_a * (double)B.l;
+    if (kernel == 1) return 2.0 * (double)B.n_a * (double)A.l;
+    const int ks = std::max((A.max_s + 3) / 4, 1);
+    const int nmt = (c.P + 15) / 16;
+    (void)precision;
+    const bool tile = ks <= 32 && nmt <= 16 && 4 * ks * kTW <= kXPT * 64 * nmt;
+    if (!tile) return 2.0 * (double)A.n_s * (double)B.n_s;
+    std::vector<int64_t> ptr((size_t)A.l + 1);
+    TB_HIP(hipMemcpy(ptr.data(), A.s_ptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    double kp = 0.0;
+    for (int64_t i = 0; i < A.l; ++i) kp += (double)(4 * ((ptr[i + 1] - ptr[i] + 3) / 4));
+    const double cols = (double)((B.l + kTW - 1) / kTW) * kTW;
+    return 2.0 * kp * (16.0 * nmt) * cols;
 }
 
 }  // namespace tbsci

@@ -124,6 +124,7 @@ void launch_diag_argmin(const Ctx &c, double *part_val, int64_t *part_idx, int n
 
 // ---- launchers (sigma_kernels.hip)
 void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms = 7);
+double executed_flops(Ctx &c, int kernel, int precision);
 
 // ---- davidson.hip
 int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *C_out,

@@ -82,6 +82,7 @@ def load():
         "tbsci_get_list": (c_int, [P, c_int, c_int, P, P, P]),
         "tbsci_timing_enable": (c_int, [P, c_int]),
         "tbsci_timing_read": (c_int, [P, c_int, c_int, P, P, P, P, P]),
+        "tbsci_timing_executed_flops": (c_int, [P, c_int, c_int, P]),
         "tbsci_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -218,6 +219,13 @@ def tbsci_timing_read(ctx, kernel, precision=TBSCI_FP64):
                 bytes=by.value)
 
 
+def tbsci_timing_executed_flops(ctx, kernel, precision=TBSCI_FP64):
+    fl = ctypes.c_double()
+    _check(load().tbsci_timing_executed_flops(ctx, int(kernel), int(precision),
+                                              ctypes.byref(fl)))
+    return fl.value
+
+
 # ---------------------------------------------------------------- wrapper
 
 class Context:
@@ -251,6 +259,10 @@ class Context:
 
     def _dev(self):
         return torch.device("cuda", self.device)
+
+    def mfma_flops(self, precision=TBSCI_FP64):
+        """Flops one launch of the opposite-spin kernel executes (padded tiles)."""
+        return tbsci_timing_executed_flops(self._ctx, 2, precision)
 
     def sigma(self, C, out=None, precision=TBSCI_FP64, stream=None):
         dt = torch.float64 if precision == TBSCI_FP64 else torch.float32

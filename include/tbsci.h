@@ -154,7 +154,13 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
  *
  *   opts      host, NULL for defaults
  *   guess_dev device double [l_alpha][l_beta] or NULL (unit vector on the
- *             smallest diagonal element, first on ties)
+ *             smallest diagonal element, first in row-major order on ties;
+ *             when the alpha and beta lists are the same strings in the
+ *             same order and N_alpha = N_beta, H commutes with the spin
+ *             flip C -> C^T and an open-shell start |I J> is replaced by
+ *             (|I J> + |J I>)/sqrt 2: the solve then stays in the C = C^T
+ *             sector, which holds the singlets, and returns its lowest
+ *             state)
  *   C_out_dev device double [l_alpha][l_beta] or NULL: receives the Ritz
  *             vector (unit norm, largest-magnitude entry positive)
  *   info      host, required
@@ -167,6 +173,114 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
  */
 int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double *guess_dev,
                    double *C_out_dev, tbsci_davidson_info *info, void *stream);
+
+/*
+ * Batched forms for many small problems on one device.  The work of all
+ * n contexts is issued together: each kernel type of the sigma build runs
+ * as one launch over every problem (the opposite-spin term one launch per
+ * group of problems with the same orbital count and tile depth), and the
+ * Davidson vector operations of all problems likewise, so that launch and
+ * synchronisation costs are paid once per batch instead of once per
+ * problem.  The arithmetic of each problem is that of the single-problem
+ * call; reductions do not depend on the other members of the batch.
+ *
+ * tbsci_sigma_batch: sigma_dev[i] = P H P C_dev[i] for ctxs[i], i < n
+ * (n <= 64, distinct contexts on one device, device arrays as in
+ * tbsci_sigma, all of the given precision).  Synchronous with respect to
+ * the host.
+ */
+int tbsci_sigma_batch(tbsci_ctx *const *ctxs, int n, const void *const *C_dev,
+                      void *const *sigma_dev, int precision, void *stream);
+
+/*
+ * tbsci_davidson_batch: the lowest eigenvalue of every problem, solved in
+ * lock step (one Davidson iteration of every unfinished problem per round,
+ * one host synchronisation per round).  opts: NULL for defaults, else an
+ * array of n (n_max at most 16).  infos[i] and status[i] (TBSCI_OK or
+ * TBSCI_E_NOTCONV) receive problem i's result.  The start vector is that
+ * of tbsci_davidson without a guess.  Eigenvectors are not
+ * returned.  Each problem holds (2 n_max + 6) FP64 vectors, plus two FP32
+ * vectors for TBSCI_MIXED, while it runs.  Returns TBSCI_OK when every
+ * problem ran (whatever its own status), else an error code.
+ */
+int tbsci_davidson_batch(tbsci_ctx *const *ctxs, int n, const tbsci_davidson_opts *opts,
+                         tbsci_davidson_info *infos, int *status, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: ground-state solves of many problems on one device, submitted
+ * and collected asynchronously (a deployment of the Davidson solver above;
+ * the paper's method is the per-request solve).
+ *
+ * A server owns four host threads.  Requests are admitted in arrival order
+ * while their device footprint fits hbm_budget_bytes (later requests that
+ * fit are admitted when the head of the queue does not); the footprint is
+ * first counted as an upper bound from the problem shape and, once the
+ * request's lists are built, trimmed to the bytes it holds.  Requests of
+ * at most batch_ndet_threshold determinants (and n_max <= 16) run in the
+ * batched solver: they join and leave between its rounds (continuous
+ * batching), share its grouped sigma and vector launches, and keep their
+ * Davidson subspaces in device memory until they finish.  Larger requests
+ * run the single-problem solver on one of two streams of their own, at the
+ * same time as the batch.  No eigenvectors are returned.
+ */
+typedef struct tbsci_server tbsci_server;
+
+typedef struct {
+    size_t hbm_budget;          /* bytes                                          */
+    size_t hbm_reserved;        /* bytes held by admitted requests now            */
+    size_t hbm_reserved_peak;   /* largest hbm_reserved so far (<= hbm_budget)    */
+    int64_t submitted, completed, failed; /* failed: completed with an error     */
+    int64_t queued;             /* waiting for admission                          */
+    int64_t running_batched, running_solo;
+    int64_t ticks;              /* rounds of the batched solver                   */
+    int max_batch;              /* most requests in one round                     */
+} tbsci_server_info;
+
+/*
+ * Start a server on `device`.  TBSCI_E_INVAL for a zero budget, a negative
+ * threshold or a bad device.
+ */
+int tbsci_server_create(int device, size_t hbm_budget_bytes, int64_t batch_ndet_threshold,
+                        tbsci_server **out);
+
+/*
+ * Stop: queued requests end with TBSCI_E_STATE ("cancelled"), running ones
+ * are stopped at their next iteration, threads are joined and every device
+ * allocation is freed.  NULL-safe.  Tickets are invalid afterwards.
+ */
+void tbsci_server_destroy(tbsci_server *server);
+
+/*
+ * Queue one ground-state solve.  Arguments as tbsci_create plus Davidson
+ * options (NULL for defaults); every host array is copied before the call
+ * returns.  Invalid inputs return TBSCI_E_INVAL and a request whose
+ * footprint bound exceeds the whole budget TBSCI_E_NOMEM, both without a
+ * ticket.  Thread-safe.
+ */
+int tbsci_submit(tbsci_server *server, int M, int n_alpha, int n_beta, const double *h,
+                 const double *eri, const uint64_t *alpha, int64_t l_alpha,
+                 const uint64_t *beta, int64_t l_beta, const tbsci_davidson_opts *opts,
+                 uint64_t *ticket);
+
+/*
+ * State of a request: TBSCI_PENDING while queued or running; when done its
+ * status (TBSCI_OK, TBSCI_E_NOTCONV, or the error that ended it, with the
+ * message in tbsci_last_error) and, if out is not NULL, its result.
+ * TBSCI_E_NOTFOUND for an unknown ticket.  Thread-safe; does not block.
+ */
+int tbsci_poll(tbsci_server *server, uint64_t ticket, tbsci_davidson_info *out);
+
+/*
+ * For a finished request: seconds from submission to admission (queue_s)
+ * and to completion (latency_s), whether it ran batched, and the device
+ * bytes it held.  TBSCI_PENDING while not finished, TBSCI_E_NOTFOUND for an
+ * unknown ticket.  Any output pointer may be NULL.
+ */
+int tbsci_request_times(tbsci_server *server, uint64_t ticket, double *queue_s,
+                        double *latency_s, int *batched, int64_t *footprint_bytes);
+
+/* Counters of the server (a consistent snapshot). */
+int tbsci_server_stats(tbsci_server *server, tbsci_server_info *out);
 
 /* ------------------------------------------------------------------------
  * Inspection of the create-time structures, for verification.

@@ -77,6 +77,8 @@ void free_spin(Spin &s) {
     s = Spin{};
 }
 
+}  // namespace
+
 void destroy_ctx(Ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
@@ -87,6 +89,8 @@ void destroy_ctx(Ctx *c) {
         if (p) (void)hipFree(p);
     delete c;
 }
+
+namespace {
 
 void check_device_ptr(const void *p, int device, const char *name) {
     if (!p) throw Error(TBSCI_E_INVAL, std::string(name) + " is NULL");
@@ -120,22 +124,84 @@ extern "C" {
 
 const char *tbsci_last_error(void) { return g_err.c_str(); }
 
-int tbsci_create(int M, int n_alpha, int n_beta, const double *h, const double *eri,
-                 const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta, int64_t l_beta,
-                 int device, tbsci_ctx **out) {
-    return guarded([&]() -> int {
-        if (!out) throw Error(TBSCI_E_INVAL, "out is NULL");
-        if (M < 1 || M > 64) throw Error(TBSCI_E_INVAL, "M must be in [1, 64]");
-        if (n_alpha < 0 || n_alpha > M || n_beta < 0 || n_beta > M)
-            throw Error(TBSCI_E_INVAL, "electron counts must be in [0, M]");
-        check_strings("alpha", alpha, l_alpha, M, n_alpha);
-        check_strings("beta", beta, l_beta, M, n_beta);
-        check_integrals(M, h, eri);
-        int ndev = 0;
-        TB_HIP(hipGetDeviceCount(&ndev));
-        if (device < 0 || device >= ndev) throw Error(TBSCI_E_INVAL, "no such device");
-        TB_HIP(hipSetDevice(device));
+}  // extern "C"
 
+namespace tbsci {
+
+void validate_problem(int M, int n_alpha, int n_beta, const double *h, const double *eri,
+                      const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta,
+                      int64_t l_beta) {
+    if (M < 1 || M > 64) throw Error(TBSCI_E_INVAL, "M must be in [1, 64]");
+    if (n_alpha < 0 || n_alpha > M || n_beta < 0 || n_beta > M)
+        throw Error(TBSCI_E_INVAL, "electron counts must be in [0, M]");
+    check_strings("alpha", alpha, l_alpha, M, n_alpha);
+    check_strings("beta", beta, l_beta, M, n_beta);
+    check_integrals(M, h, eri);
+}
+
+void check_device_index(int device) {
+    int ndev = 0;
+    TB_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) throw Error(TBSCI_E_INVAL, "no such device");
+}
+
+namespace {
+
+size_t page(size_t bytes) { return (std::max<size_t>(bytes, 8) + 4095) & ~size_t(4095); }
+
+// allocation sizes of one spin's structures (see build_spin), cnt included
+size_t spin_bytes(int M, int P, int n, int64_t l, int64_t n_s, int64_t n_d) {
+    const size_t L = (size_t)l;
+    const int64_t n_a = l + (n_s - (int64_t)n * l) + n_d;
+    const size_t ngroup = 4 * (size_t)((P + 15) / 16);
+    return page(8 * L) * 2 + page(4 * L) + page(8 * L) + page(8 * (L + 1)) * 3 +
+           page(8 * (size_t)n_s) * 2 + page(4 * L * (ngroup + 1)) + page(8 * (size_t)n_d) +
+           page(8 * L) + page(8 * L * (size_t)M) + page(4 * (size_t)n_a) +
+           page(8 * (size_t)n_a) + page(4 * (size_t)n_a);
+}
+
+size_t fixed_bytes(int M, int P, int64_t l_alpha, int64_t l_beta) {
+    const size_t M2 = (size_t)M * M, PP = (size_t)P * P;
+    const size_t nd = (size_t)(l_alpha * l_beta);
+    return page(8 * M2) + page(8 * M2 * M2) + page(8 * PP) + page(4 * PP) + page(16 * nd);
+}
+
+double binom(int n, int k) {
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+}  // namespace
+
+size_t ctx_bytes(const Ctx &c) {
+    return fixed_bytes(c.M, c.P, c.sp[0].l, c.sp[1].l) +
+           spin_bytes(c.M, c.P, c.sp[0].n, c.sp[0].l, c.sp[0].n_s, c.sp[0].n_d) +
+           spin_bytes(c.M, c.P, c.sp[1].n, c.sp[1].l, c.sp[1].n_s, c.sp[1].n_d);
+}
+
+size_t ctx_bytes_bound(int M, int n_alpha, int n_beta, int64_t l_alpha, int64_t l_beta) {
+    const int P = M * (M + 1) / 2;
+    size_t b = fixed_bytes(M, P, l_alpha, l_beta);
+    const int ns[2] = {n_alpha, n_beta};
+    const int64_t ls[2] = {l_alpha, l_beta};
+    for (int s = 0; s < 2; ++s) {
+        const int n = ns[s];
+        const int64_t l = ls[s];
+        // each string links to at most l - 1 others, and to at most the
+        // complete-space counts n (M - n) singles and C(n,2) C(M-n,2) doubles
+        const double s_off = std::min((double)n * (M - n), (double)(l - 1));
+        const double d_max = std::min(binom(n, 2) * binom(M - n, 2), (double)(l - 1));
+        b += spin_bytes(M, P, n, l, (int64_t)((double)l * (n + s_off)), (int64_t)((double)l * d_max));
+    }
+    return b;
+}
+
+Ctx *create_ctx(int M, int n_alpha, int n_beta, const double *h, const double *eri,
+                const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta, int64_t l_beta,
+                int device) {
+        TB_HIP(hipSetDevice(device));
         Ctx *c = new Ctx();
         try {
             c->M = M;
@@ -145,6 +211,8 @@ int tbsci_create(int M, int n_alpha, int n_beta, const double *h, const double *
             c->sp[0].l = l_alpha;
             c->sp[1].n = n_beta;
             c->sp[1].l = l_beta;
+            c->flip = n_alpha == n_beta && l_alpha == l_beta &&
+                      std::equal(alpha, alpha + l_alpha, beta);
             const size_t M2 = (size_t)M * M, M4 = M2 * M2, P = c->P;
             std::vector<double> V64(P * P);
             std::vector<float> V32(P * P);
@@ -183,7 +251,22 @@ int tbsci_create(int M, int n_alpha, int n_beta, const double *h, const double *
             destroy_ctx(c);
             throw;
         }
-        *out = (tbsci_ctx *)c;
+        return c;
+}
+
+}  // namespace tbsci
+
+extern "C" {
+
+int tbsci_create(int M, int n_alpha, int n_beta, const double *h, const double *eri,
+                 const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta, int64_t l_beta,
+                 int device, tbsci_ctx **out) {
+    return guarded([&]() -> int {
+        if (!out) throw Error(TBSCI_E_INVAL, "out is NULL");
+        validate_problem(M, n_alpha, n_beta, h, eri, alpha, l_alpha, beta, l_beta);
+        check_device_index(device);
+        *out = (tbsci_ctx *)create_ctx(M, n_alpha, n_beta, h, eri, alpha, l_alpha, beta, l_beta,
+                                       device);
         return TBSCI_OK;
     });
 }

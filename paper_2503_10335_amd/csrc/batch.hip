@@ -1,0 +1,969 @@
+// Lock-step batched Davidson (grouped vector kernels, the engine, and the
+// C entry points tbsci_sigma_batch / tbsci_davidson_batch).  The iteration
+// is the single-problem solver's (paper Sec. II.B Davidson on the sigma
+// product, Sec. III.C bounded restart, Sec. III.A single-precision sigma
+// with double precision elsewhere); what differs is only how the work of
+// many problems is issued.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "batch.hpp"
+
+namespace tbsci {
+
+void jacobi_eigh(int k, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z);
+
+namespace {
+
+constexpr int kB = 256;
+constexpr int kSV = kBatchMaxVec;
+constexpr int kNbMax = 256;
+// scalar area of a slot (doubles)
+constexpr int sCol = 0;         // [kSV] V_i . W_new
+constexpr int sR2 = kSV;        // |r|^2 of the tick's Ritz pair
+constexpr int sTn0 = kSV + 1;   // |t|^2 before Gram-Schmidt
+constexpr int sTn2 = kSV + 2;   // |t|^2 after Gram-Schmidt (t normalised first)
+constexpr int sN2 = kSV + 3;    // |previous direction|^2 after re-orthogonalisation
+constexpr int sG = kSV + 4;     // x.Wx, x.Wxp, xp.Wx, xp.Wxp
+constexpr int sArg = kSV + 8;   // start index
+constexpr int sCoef = 2 * kSV;  // [kSV] projection coefficients
+constexpr int kScal = 4 * kSV;  // row length
+static_assert(sCoef + kSV <= kScal, "scalar area");
+
+// One slot's part of a grouped launch.  Grid-stride kernels give slot d the
+// blocks [blk0, blk0 + nb); the reduce and start kernels index d directly.
+struct VDesc {
+    int64_t blk0, n;
+    int32_t nb, k;
+    int32_t dst, src;  // scalar-area indices (reduce target; coefficient / norm source)
+    double thresh;     // scale: norms at or below it scale by 0
+    double *o0, *o1, *o2;
+    const double *in;
+    float *f;
+    double *partial, *scal;
+    const double *a[kSV];
+    const double *b[kSV];
+    double c[kSV];
+    double theta, floor_;
+    int64_t lb;
+    int32_t M, flip;
+    const uint64_t *astr;
+    const double *da, *db, *jb;
+};
+
+__device__ __forceinline__ const VDesc &slot_of(const VDesc *__restrict__ d, int nd, int64_t &lblk) {
+    int lo = 0, hi = nd - 1;
+    const int64_t b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].blk0 <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    lblk = b - d[lo].blk0;
+    return d[lo];
+}
+
+__device__ __forceinline__ double block_sum(double s, double *red) {
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+#define TB_SLOT_LOOP(e, lblk, t) \
+    for (int64_t t = lblk * kB + threadIdx.x; t < e.n; t += (int64_t)e.nb * kB)
+
+// H_KK from the per-string parts (as in the single solver)
+__device__ __forceinline__ double diag_at(const VDesc &e, int64_t t) {
+    const int64_t ia = t / e.lb, ib = t - ia * e.lb;
+    double d = e.da[ia] + e.db[ib];
+    const double *jr = e.jb + ib * e.M;
+    for (uint64_t m = e.astr[ia]; m; m &= m - 1) d += jr[__builtin_ctzll(m)];
+    return d;
+}
+
+__global__ __launch_bounds__(kB) void gv_fill(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    TB_SLOT_LOOP(e, lb, t) e.o0[t] = 0.0;
+}
+
+// per block: smallest H_KK and its first index
+__global__ __launch_bounds__(kB) void gv_diag_min(const VDesc *__restrict__ d, int nd) {
+    __shared__ double sv[kB];
+    __shared__ int64_t si[kB];
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    double best = 1e308;
+    int64_t bi = -1;
+    TB_SLOT_LOOP(e, lb, t) {
+        const double v = diag_at(e, t);
+        if (v < best) {
+            best = v;
+            bi = t;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            const double v2 = sv[threadIdx.x + off];
+            const int64_t i2 = si[threadIdx.x + off];
+            if (i2 >= 0 && (v2 < sv[threadIdx.x] ||
+                            (v2 == sv[threadIdx.x] && (si[threadIdx.x] < 0 || i2 < si[threadIdx.x])))) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        e.partial[lb] = sv[0];
+        e.partial[kNbMax + lb] = (double)si[0];
+    }
+}
+
+// one block per slot: the start vector is the unit vector on the smallest
+// H_KK (first on ties)
+__global__ __launch_bounds__(kB) void gv_argmin_unit(const VDesc *__restrict__ d) {
+    const VDesc &e = d[blockIdx.x];
+    __shared__ double sv[kB];
+    __shared__ int64_t si[kB];
+    double best = 1e308;
+    int64_t bi = -1;
+    for (int b = threadIdx.x; b < e.nb; b += kB) {
+        const double v = e.partial[b];
+        const int64_t i = (int64_t)e.partial[kNbMax + b];
+        if (i >= 0 && (v < best || (v == best && (bi < 0 || i < bi)))) {
+            best = v;
+            bi = i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            const double v2 = sv[threadIdx.x + off];
+            const int64_t i2 = si[threadIdx.x + off];
+            if (i2 >= 0 && (v2 < sv[threadIdx.x] ||
+                            (v2 == sv[threadIdx.x] && (si[threadIdx.x] < 0 || i2 < si[threadIdx.x])))) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // in a flip-symmetric space an open-shell |I J> is paired with |J I>
+        const int64_t at = si[0] >= 0 ? si[0] : 0;
+        const int64_t ia = at / e.lb, ib = at - ia * e.lb;
+        const int64_t at2 = e.flip ? ib * e.lb + ia : at;
+        const double val = at2 == at ? 1.0 : 0.70710678118654752440;
+        e.o0[at] = val;
+        e.o0[at2] = val;
+        e.scal[e.dst] = (double)at;
+    }
+}
+
+// x = V y, wx = W y, t = (wx - theta x) / (theta - H_KK) with a floor;
+// partial sums of |wx - theta x|^2
+__global__ __launch_bounds__(kB) void gv_ritz(const VDesc *__restrict__ d, int nd) {
+    __shared__ double red[kB];
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    double s = 0.0;
+    TB_SLOT_LOOP(e, lb, t) {
+        double xv = 0.0, wv = 0.0;
+        for (int i = 0; i < e.k; ++i) {
+            xv += e.c[i] * e.a[i][t];
+            wv += e.c[i] * e.b[i][t];
+        }
+        const double r = wv - e.theta * xv;
+        s += r * r;
+        double den = e.theta - diag_at(e, t);
+        if (fabs(den) < e.floor_) den = den < 0.0 ? -e.floor_ : e.floor_;
+        e.o0[t] = xv;
+        e.o1[t] = wv;
+        e.o2[t] = r / den;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) e.partial[lb] = s;
+}
+
+// o0 = sum_i c_i a_i, o1 = sum_i c_i b_i
+__global__ __launch_bounds__(kB) void gv_lincomb2(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    TB_SLOT_LOOP(e, lb, t) {
+        double xv = 0.0, wv = 0.0;
+        for (int i = 0; i < e.k; ++i) {
+            xv += e.c[i] * e.a[i][t];
+            wv += e.c[i] * e.b[i][t];
+        }
+        e.o0[t] = xv;
+        e.o1[t] = wv;
+    }
+}
+
+// partial[i][blk] = block's part of a_i . in, i < k
+__global__ __launch_bounds__(kB) void gv_dots(const VDesc *__restrict__ d, int nd) {
+    __shared__ double red[kB];
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    for (int i = 0; i < e.k; ++i) {
+        const double *__restrict__ ai = e.a[i];
+        double s = 0.0;
+        TB_SLOT_LOOP(e, lb, t) s += ai[t] * e.in[t];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) e.partial[i * kNbMax + lb] = s;
+    }
+}
+
+// scal[dst + i] = sum over the slot's blocks of partial[i][.]; block = (slot, i)
+__global__ __launch_bounds__(kB) void gv_reduce(const VDesc *__restrict__ d, int kmax) {
+    __shared__ double red[kB];
+    const VDesc &e = d[blockIdx.x / kmax];
+    const int i = blockIdx.x % kmax;
+    if (i >= e.k) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < e.nb; b += kB) s += e.partial[i * kNbMax + b];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) e.scal[e.dst + i] = s;
+}
+
+// o0 -= sum_i scal[src + i] a_i (and o1 -= sum_i scal[src + i] b_i)
+__global__ __launch_bounds__(kB) void gv_subproj(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    double cf[kSV];
+    for (int i = 0; i < e.k; ++i) cf[i] = e.scal[e.src + i];
+    TB_SLOT_LOOP(e, lb, t) {
+        double v = e.o0[t];
+        for (int i = 0; i < e.k; ++i) v -= cf[i] * e.a[i][t];
+        e.o0[t] = v;
+        if (e.o1) {
+            double w = e.o1[t];
+            for (int i = 0; i < e.k; ++i) w -= cf[i] * e.b[i][t];
+            e.o1[t] = w;
+        }
+    }
+}
+
+// o0 (and o1) *= 1 / sqrt(scal[src]), or 0 when that norm is <= thresh
+__global__ __launch_bounds__(kB) void gv_scale(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    const double nrm = sqrt(fmax(e.scal[e.src], 0.0));
+    const double f = nrm > e.thresh ? 1.0 / nrm : 0.0;
+    TB_SLOT_LOOP(e, lb, t) {
+        e.o0[t] *= f;
+        if (e.o1) e.o1[t] *= f;
+    }
+}
+
+// correction vectors of flip-symmetric slots: T = (T + T^T) / 2; d.nb is
+// the slot's tile-pair block count here
+__global__ __launch_bounds__(kB) void gv_flip_sym(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    flip_sym_block(lb, e.lb, e.o0);
+}
+
+__global__ __launch_bounds__(kB) void gv_to_f32(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    TB_SLOT_LOOP(e, lb, t) e.f[t] = (float)e.in[t];
+}
+
+__global__ __launch_bounds__(kB) void gv_to_f64(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc &e = slot_of(d, nd, lb);
+    TB_SLOT_LOOP(e, lb, t) e.o0[t] = (double)e.f[t];
+}
+
+#undef TB_SLOT_LOOP
+
+// operations of a tick, in issue order
+enum Op {
+    O_FILL, O_DMIN, O_AMIN,
+    O_RITZ, O_RITZ_R, O_SYM,
+    O_LC,
+    O_RO1_D, O_RO1_R, O_RO1_S, O_RO2_D, O_RO2_R, O_RO2_S,
+    O_N2_D, O_N2_R, O_N2_S,
+    O_G0_D, O_G0_R, O_G1_D, O_G1_R,
+    O_T0_D, O_T0_R, O_T0_S,
+    O_GS1_D, O_GS1_R, O_GS1_S, O_GS2_D, O_GS2_R, O_GS2_S,
+    O_TN_D, O_TN_R, O_TN_S,
+    O_CVT32,
+    O_SIGMA,  // marker: grouped sigma builds
+    O_CVT64,
+    O_COL_D, O_COL_R,
+    O_N
+};
+
+enum Kind {
+    K_FILL, K_DMIN, K_AMIN, K_RITZ, K_RED, K_SYM, K_LC, K_DOT, K_SUB, K_SCALE, K_F32, K_F64, K_NONE
+};
+
+Kind kind_of(int op) {
+    switch (op) {
+        case O_FILL: return K_FILL;
+        case O_DMIN: return K_DMIN;
+        case O_AMIN: return K_AMIN;
+        case O_RITZ: return K_RITZ;
+        case O_SYM: return K_SYM;
+        case O_LC: return K_LC;
+        case O_RO1_S: case O_RO2_S: case O_GS1_S: case O_GS2_S: return K_SUB;
+        case O_N2_S: case O_T0_S: case O_TN_S: return K_SCALE;
+        case O_CVT32: return K_F32;
+        case O_CVT64: return K_F64;
+        case O_SIGMA: return K_NONE;
+        case O_RITZ_R: case O_RO1_R: case O_RO2_R: case O_N2_R: case O_G0_R: case O_G1_R:
+        case O_T0_R: case O_GS1_R: case O_GS2_R: case O_TN_R: case O_COL_R: return K_RED;
+        default: return K_DOT;
+    }
+}
+
+int blocks_for_slot(int64_t n) {
+    return (int)std::min<int64_t>(kNbMax, std::max<int64_t>(1, (n + 4 * kB - 1) / (4 * kB)));
+}
+
+size_t page(size_t bytes) { return (std::max<size_t>(bytes, 8) + 4095) & ~size_t(4095); }
+
+}  // namespace
+
+struct BatchEngine::Stage {
+    std::vector<VDesc> ops[O_N];
+    std::vector<Ctx *> c64, c32;
+    std::vector<const void *> i64, i32;
+    std::vector<void *> o64, o32;
+};
+
+BatchEngine::BatchEngine(int device, hipStream_t st) : device_(device), st_(st), ar_(8u << 20) {
+    TB_HIP(hipMalloc((void **)&scal_dev_, sizeof(double) * kScal * kBatchMaxSlots));
+    TB_HIP(hipHostMalloc((void **)&scal_host_, sizeof(double) * kScal * kBatchMaxSlots,
+                         hipHostMallocDefault));
+    TB_HIP(hipEventCreate(&ev_[0]));
+    TB_HIP(hipEventCreate(&ev_[1]));
+    for (int r = kBatchMaxSlots - 1; r >= 0; --r) free_rows_.push_back(r);
+}
+
+BatchEngine::~BatchEngine() {
+    for (auto &e : ev_)
+        if (e) (void)hipEventDestroy(e);
+    if (scal_dev_) (void)hipFree(scal_dev_);
+    if (scal_host_) (void)hipHostFree(scal_host_);
+}
+
+size_t BatchEngine::slot_bytes(int64_t n, const tbsci_davidson_opts &o) {
+    const size_t v = page(8 * (size_t)n);
+    size_t b = 2 * (size_t)(o.n_max + 3) * v + page(8 * (size_t)kSV * kNbMax);
+    if (o.precision == TBSCI_MIXED) b += 2 * page(4 * (size_t)n);
+    return b;
+}
+
+BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o) {
+    auto *s = new BatchSlot();
+    try {
+        s->c = c;
+        s->o = o;
+        s->n = c->sp[0].l * c->sp[1].l;
+        s->nb = blocks_for_slot(s->n);
+        auto get = [&](size_t bytes) {
+            void *p = nullptr;
+            TB_HIP(hipMalloc(&p, bytes));
+            s->all.push_back((double *)p);
+            s->bytes += page(bytes);
+            return p;
+        };
+        for (int i = 0; i < o.n_max + 3; ++i) {
+            s->vfree.push_back((double *)get(8 * (size_t)s->n));
+            s->wfree.push_back((double *)get(8 * (size_t)s->n));
+        }
+        s->partial = (double *)get(8 * (size_t)kSV * kNbMax);
+        if (o.precision == TBSCI_MIXED) {
+            s->f32a = (float *)get(4 * (size_t)s->n);
+            s->f32b = (float *)get(4 * (size_t)s->n);
+        }
+        s->G.assign((size_t)o.n_max * o.n_max, 0.0);
+    } catch (...) {
+        free_slot(s);
+        throw;
+    }
+    return s;
+}
+
+void BatchEngine::free_slot(BatchSlot *s) {
+    if (!s) return;
+    for (double *p : s->all)
+        if (p) (void)hipFree(p);
+    delete s;
+}
+
+void BatchEngine::add(BatchSlot *s) {
+    if (free_rows_.empty()) throw Error(TBSCI_E_STATE, "batch is full");
+    s->row = free_rows_.back();
+    free_rows_.pop_back();
+    s->phase = BatchSlot::kStart;
+    s->fp32 = s->o.precision == TBSCI_MIXED;
+    s->t0 = std::chrono::steady_clock::now();
+    memset(&s->info, 0, sizeof(s->info));
+    act_.push_back(s);
+}
+
+std::vector<BatchSlot *> BatchEngine::take_done() {
+    std::vector<BatchSlot *> d;
+    d.swap(done_);
+    return d;
+}
+
+std::vector<BatchSlot *> BatchEngine::drain() {
+    std::vector<BatchSlot *> v;
+    v.swap(act_);
+    for (BatchSlot *s : v) {
+        free_rows_.push_back(s->row);
+        s->row = -1;
+    }
+    return v;
+}
+
+void BatchEngine::plan(BatchSlot &s, Stage &S) {
+    auto &P = s.p;
+    P = BatchSlot::Plan{};
+    double *scal = scal_dev_ + (size_t)s.row * kScal;
+    auto base = [&]() {
+        VDesc d{};
+        d.n = s.n;
+        d.nb = s.nb;
+        d.partial = s.partial;
+        d.scal = scal;
+        return d;
+    };
+    auto dots = [&](int op, const std::vector<double *> &a, const double *in, int dst) {
+        VDesc d = base();
+        d.k = (int)a.size();
+        for (int i = 0; i < d.k; ++i) d.a[i] = a[i];
+        d.in = in;
+        S.ops[op].push_back(d);
+        VDesc r = base();
+        r.k = d.k;
+        r.dst = dst;
+        S.ops[op + 1].push_back(r);
+    };
+    auto subproj = [&](int op, double *o0, const std::vector<double *> &a, double *o1,
+                       const std::vector<double *> &b) {
+        VDesc d = base();
+        d.k = (int)a.size();
+        for (int i = 0; i < d.k; ++i) {
+            d.a[i] = a[i];
+            d.b[i] = o1 ? b[i] : nullptr;
+        }
+        d.o0 = o0;
+        d.o1 = o1;
+        d.src = sCoef;
+        S.ops[op].push_back(d);
+    };
+    auto scale = [&](int op, double *o0, double *o1, int src, double thresh) {
+        VDesc d = base();
+        d.o0 = o0;
+        d.o1 = o1;
+        d.src = src;
+        d.thresh = thresh;
+        S.ops[op].push_back(d);
+    };
+    auto diag_fields = [&](VDesc &d) {
+        d.lb = s.c->sp[1].l;
+        d.M = s.c->M;
+        d.astr = s.c->sp[0].str;
+        d.da = s.c->sp[0].dsame;
+        d.db = s.c->sp[1].dsame;
+        d.jb = s.c->sp[1].jocc;
+    };
+    auto take = [](std::vector<double *> &pool) {
+        if (pool.empty()) throw Error(TBSCI_E_STATE, "batch slot vector pool exhausted");
+        double *p = pool.back();
+        pool.pop_back();
+        return p;
+    };
+    const double *sig_in = nullptr;
+    double *sig_out = nullptr;
+
+    if (s.phase == BatchSlot::kStart || s.phase == BatchSlot::kHandover) {
+        if (s.phase == BatchSlot::kStart) {
+            P.V0 = take(s.vfree);
+            VDesc f = base();
+            f.o0 = P.V0;
+            S.ops[O_FILL].push_back(f);
+            VDesc m = base();
+            diag_fields(m);
+            S.ops[O_DMIN].push_back(m);
+            VDesc u = base();
+            u.o0 = P.V0;
+            u.dst = sArg;
+            u.lb = s.c->sp[1].l;
+            u.flip = s.c->flip ? 1 : 0;
+            S.ops[O_AMIN].push_back(u);
+        } else {
+            P.V0 = s.X;  // the Ritz vector of the FP32 phase
+            s.X = nullptr;
+        }
+        P.W0 = take(s.wfree);
+        P.sig32 = s.phase == BatchSlot::kStart && s.fp32;
+        sig_in = P.V0;
+        sig_out = P.W0;
+        dots(O_COL_D, {P.V0}, P.W0, sCol);
+    } else {
+        // Rayleigh-Ritz on the k x k projected matrix
+        const int k = s.k, nm = s.o.n_max;
+        std::vector<double> Gk((size_t)k * k), w, Z;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) Gk[i * k + j] = 0.5 * (s.G[i * nm + j] + s.G[j * nm + i]);
+        jacobi_eigh(k, Gk, w, Z);
+        int lo = 0;
+        for (int i = 1; i < k; ++i)
+            if (w[i] < w[lo]) lo = i;
+        s.theta_prev = s.theta;
+        s.theta = w[lo];
+        s.y.assign(k, 0.0);
+        for (int i = 0; i < k; ++i) s.y[i] = Z[i * k + lo];
+        std::vector<double> yp = s.yprev;
+        yp.resize(k, 0.0);
+        s.yprev = s.y;
+
+        P.Xn = take(s.vfree);
+        P.WXn = take(s.wfree);
+        P.T = take(s.vfree);
+        P.TW = take(s.wfree);
+        P.sig32 = s.fp32;
+        VDesc r = base();
+        diag_fields(r);
+        r.k = k;
+        for (int i = 0; i < k; ++i) {
+            r.a[i] = s.V[i];
+            r.b[i] = s.W[i];
+            r.c[i] = s.y[i];
+        }
+        r.theta = s.theta;
+        r.floor_ = s.o.precond_floor;
+        r.o0 = P.Xn;
+        r.o1 = P.WXn;
+        r.o2 = P.T;
+        S.ops[O_RITZ].push_back(r);
+        VDesc rr = base();
+        rr.k = 1;
+        rr.dst = sR2;
+        S.ops[O_RITZ_R].push_back(rr);
+        if (s.c->flip) {  // keep the solve in the C = C^T sector
+            VDesc y = base();
+            const int64_t l = s.c->sp[1].l, nt = (l + 31) / 32;
+            y.nb = (int32_t)(nt * nt);
+            y.lb = l;
+            y.o0 = P.T;
+            S.ops[O_SYM].push_back(y);
+        }
+
+        P.restart = k >= nm;
+        if (P.restart) {
+            // keep x = V y and the part of the previous Ritz vector
+            // orthogonal to it, z = yp - (yp.y) y (when there is room)
+            std::vector<double> z(k);
+            double dz = 0.0, nz = 0.0;
+            for (int i = 0; i < k; ++i) dz += yp[i] * s.y[i];
+            for (int i = 0; i < k; ++i) {
+                z[i] = yp[i] - dz * s.y[i];
+                nz += z[i] * z[i];
+            }
+            nz = std::sqrt(nz);
+            if (nz > 1e-8 && nm >= 3) {
+                P.took_xp = true;
+                P.XP = take(s.vfree);
+                P.WXP = take(s.wfree);
+                VDesc l = base();
+                l.k = k;
+                for (int i = 0; i < k; ++i) {
+                    l.a[i] = s.V[i];
+                    l.b[i] = s.W[i];
+                    l.c[i] = z[i] / nz;
+                }
+                l.o0 = P.XP;
+                l.o1 = P.WXP;
+                S.ops[O_LC].push_back(l);
+                // V z is a difference of nearly equal vectors near
+                // convergence: re-orthogonalise against x twice, with the
+                // same combination on its image
+                dots(O_RO1_D, {P.Xn}, P.XP, sCoef);
+                subproj(O_RO1_S, P.XP, {P.Xn}, P.WXP, {P.WXn});
+                dots(O_RO2_D, {P.Xn}, P.XP, sCoef);
+                subproj(O_RO2_S, P.XP, {P.Xn}, P.WXP, {P.WXn});
+                dots(O_N2_D, {P.XP}, P.XP, sN2);
+                scale(O_N2_S, P.XP, P.WXP, sN2, 1e-8);
+                dots(O_G0_D, {P.WXn, P.WXP}, P.Xn, sG);
+                dots(O_G1_D, {P.WXn, P.WXP}, P.XP, sG + 2);
+                P.Vb = {P.Xn, P.XP};
+                P.Wb = {P.WXn, P.WXP};
+            } else {
+                dots(O_G0_D, {P.WXn}, P.Xn, sG);
+                P.Vb = {P.Xn};
+                P.Wb = {P.WXn};
+            }
+        } else {
+            P.Vb = s.V;
+            P.Wb = s.W;
+        }
+        // normalise t (the drop test is relative), two Gram-Schmidt passes
+        // against the basis it joins, normalise again
+        dots(O_T0_D, {P.T}, P.T, sTn0);
+        scale(O_T0_S, P.T, nullptr, sTn0, 0.0);
+        dots(O_GS1_D, P.Vb, P.T, sCoef);
+        subproj(O_GS1_S, P.T, P.Vb, nullptr, {});
+        dots(O_GS2_D, P.Vb, P.T, sCoef);
+        subproj(O_GS2_S, P.T, P.Vb, nullptr, {});
+        dots(O_TN_D, {P.T}, P.T, sTn2);
+        scale(O_TN_S, P.T, nullptr, sTn2, 1e-10);
+        sig_in = P.T;
+        sig_out = P.TW;
+        std::vector<double *> all = P.Vb;
+        all.push_back(P.T);
+        dots(O_COL_D, all, P.TW, sCol);
+    }
+    if (P.sig32) {
+        VDesc a = base();
+        a.in = sig_in;
+        a.f = s.f32a;
+        S.ops[O_CVT32].push_back(a);
+        S.c32.push_back(s.c);
+        S.i32.push_back(s.f32a);
+        S.o32.push_back(s.f32b);
+        VDesc b = base();
+        b.f = s.f32b;
+        b.o0 = sig_out;
+        S.ops[O_CVT64].push_back(b);
+    } else {
+        S.c64.push_back(s.c);
+        S.i64.push_back(sig_in);
+        S.o64.push_back(sig_out);
+    }
+}
+
+bool BatchEngine::tick() {
+    if (act_.empty()) return false;
+    TB_HIP(hipSetDevice(device_));
+    ar_.reset();
+    Stage S;
+    for (BatchSlot *s : act_) plan(*s, S);
+    max_group = std::max(max_group, (int)act_.size());
+
+    // stage every table of the tick, one transfer
+    const VDesc *dev[O_N] = {};
+    int64_t blocks[O_N] = {};
+    int kmax[O_N] = {};
+    for (int op = 0; op < O_N; ++op) {
+        auto &v = S.ops[op];
+        if (v.empty()) continue;
+        const Kind kd = kind_of(op);
+        if (kd == K_RED) {
+            for (auto &d : v) kmax[op] = std::max(kmax[op], (int)d.k);
+            blocks[op] = (int64_t)v.size() * kmax[op];
+        } else if (kd == K_AMIN) {
+            blocks[op] = (int64_t)v.size();
+        } else {
+            int64_t b = 0;
+            for (auto &d : v) {
+                d.blk0 = b;
+                b += d.nb;
+            }
+            blocks[op] = b;
+        }
+        dev[op] = ar_.stage(v.data(), v.size());
+    }
+    ar_.flush(st_);
+
+    auto launch = [&](int op) {
+        if (S.ops[op].empty()) return;
+        const unsigned g = (unsigned)blocks[op];
+        const int nd = (int)S.ops[op].size();
+        switch (kind_of(op)) {
+            case K_FILL: gv_fill<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_DMIN: gv_diag_min<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_AMIN: gv_argmin_unit<<<g, kB, 0, st_>>>(dev[op]); break;
+            case K_RITZ: gv_ritz<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_RED: gv_reduce<<<g, kB, 0, st_>>>(dev[op], kmax[op]); break;
+            case K_SYM: gv_flip_sym<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_LC: gv_lincomb2<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_DOT: gv_dots<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_SUB: gv_subproj<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_SCALE: gv_scale<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_F32: gv_to_f32<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_F64: gv_to_f64<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_NONE: break;
+        }
+        TB_HIP(hipGetLastError());
+    };
+    for (int op = 0; op < O_SIGMA; ++op) launch(op);
+    TB_HIP(hipEventRecord(ev_[0], st_));
+    if (!S.c64.empty())
+        launch_sigma_group(S.c64.data(), S.i64.data(), S.o64.data(), (int)S.c64.size(),
+                           TBSCI_FP64, ar_, st_);
+    if (!S.c32.empty())
+        launch_sigma_group(S.c32.data(), S.i32.data(), S.o32.data(), (int)S.c32.size(),
+                           TBSCI_FP32, ar_, st_);
+    launch(O_CVT64);
+    TB_HIP(hipEventRecord(ev_[1], st_));
+    for (int op = O_CVT64 + 1; op < O_N; ++op) launch(op);
+
+    int rows = 0;
+    for (BatchSlot *s : act_) rows = std::max(rows, s->row + 1);
+    TB_HIP(hipMemcpyAsync(scal_host_, scal_dev_, sizeof(double) * kScal * rows,
+                          hipMemcpyDeviceToHost, st_));
+    TB_HIP(hipStreamSynchronize(st_));
+    float ms = 0.f;
+    TB_HIP(hipEventElapsedTime(&ms, ev_[0], ev_[1]));
+    ++ticks;
+
+    std::vector<BatchSlot *> still;
+    for (BatchSlot *s : act_) {
+        commit(*s, scal_host_ + (size_t)s->row * kScal, ms * 1e-3);
+        if (s->phase == BatchSlot::kDone) {
+            free_rows_.push_back(s->row);
+            s->row = -1;
+            done_.push_back(s);
+        } else {
+            still.push_back(s);
+        }
+    }
+    act_.swap(still);
+    return true;
+}
+
+void BatchEngine::finish(BatchSlot &s, double *keep) {
+    s.phase = BatchSlot::kDone;
+    if (keep) s.vfree.push_back(keep);
+    if (s.fp32) s.info.converged = 0;  // never certified by an FP64 sigma
+    s.status = s.info.converged ? TBSCI_OK : TBSCI_E_NOTCONV;
+    s.info.energy = s.theta;
+    s.info.resid_norm = s.rn;
+    s.info.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - s.t0).count();
+}
+
+void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
+    auto &P = s.p;
+    const int nm = s.o.n_max;
+    s.info.iters++;
+    if (P.sig32)
+        s.info.iters_fp32++;
+    else
+        s.info.iters_fp64++;
+    s.info.t_sigma_s += t_sig;
+    auto release_v = [&](double *p) {
+        if (p) s.vfree.push_back(p);
+    };
+    auto release_w = [&](double *p) {
+        if (p) s.wfree.push_back(p);
+    };
+
+    if (s.phase == BatchSlot::kStart || s.phase == BatchSlot::kHandover) {
+        if (s.phase == BatchSlot::kHandover) s.fp32 = false;
+        s.V = {P.V0};
+        s.W = {P.W0};
+        std::fill(s.G.begin(), s.G.end(), 0.0);
+        s.G[0] = r[sCol];
+        s.k = 1;
+        s.theta = r[sCol];
+        s.yprev.clear();
+        s.phase = BatchSlot::kIter;
+        return;
+    }
+
+    s.rn = std::sqrt(std::max(r[sR2], 0.0));
+    const double tn = std::sqrt(std::max(r[sTn2], 0.0));
+    const bool dropped = !(tn >= 1e-10);
+    if (trace)
+        fprintf(stderr, "tbsci batch: slot %d sigma %d k %d %s theta %.15f resid %.3e\n", s.row,
+                s.info.iters, s.k, s.fp32 ? "fp32" : "fp64", s.theta, s.rn);
+
+    // everything of this tick except the Ritz vector goes back to the pools
+    auto drop_all_but_x = [&]() {
+        for (double *p : s.V) release_v(p);
+        for (double *p : s.W) release_w(p);
+        s.V.clear();
+        s.W.clear();
+        release_w(P.WXn);
+        release_v(P.T);
+        release_w(P.TW);
+        release_v(P.XP);
+        release_w(P.WXP);
+    };
+    bool handover = false;
+    if (s.fp32) {
+        // same rule as the single-problem solver
+        if (s.rn < 0.98 * s.best_rn) {
+            s.best_rn = s.rn;
+            s.since_best = 0;
+        } else {
+            ++s.since_best;
+        }
+        const bool at_floor = s.rn < 10.0 * 2e-6 * std::fabs(s.theta);
+        handover = s.rn <= s.o.fp32_switch_resid || (s.since_best >= 20 && at_floor) ||
+                   s.info.iters >= s.o.max_iter / 2 || dropped;
+    } else if (s.rn <= s.o.tol_resid &&
+               (s.o.tol_energy <= 0.0 || std::fabs(s.theta - s.theta_prev) <= s.o.tol_energy)) {
+        s.info.converged = 1;
+        drop_all_but_x();
+        finish(s, P.Xn);
+        return;
+    }
+    if (!handover && (s.info.iters >= s.o.max_iter || (!s.fp32 && dropped))) {
+        drop_all_but_x();
+        finish(s, P.Xn);  // not converged (iteration cap or stagnation)
+        return;
+    }
+    if (handover) {
+        drop_all_but_x();
+        s.X = P.Xn;
+        s.phase = BatchSlot::kHandover;
+        return;
+    }
+    // the restart (if any) becomes the basis; positions of its vectors in
+    // the column of dots
+    std::vector<int> pos;
+    if (P.restart) {
+        for (double *p : s.V) release_v(p);
+        for (double *p : s.W) release_w(p);
+        const bool two = P.took_xp && std::sqrt(std::max(r[sN2], 0.0)) > 1e-8;
+        std::fill(s.G.begin(), s.G.end(), 0.0);
+        if (two) {
+            s.V = {P.Xn, P.XP};
+            s.W = {P.WXn, P.WXP};
+            s.G[0] = r[sG];
+            s.G[1] = r[sG + 1];
+            s.G[nm] = r[sG + 2];
+            s.G[nm + 1] = r[sG + 3];
+            s.yprev = {1.0, 0.0};
+            pos = {0, 1};
+        } else {
+            release_v(P.XP);
+            release_w(P.WXP);
+            s.V = {P.Xn};
+            s.W = {P.WXn};
+            s.G[0] = r[sG];
+            s.yprev = {1.0};
+            pos = {0};
+        }
+        s.k = (int)s.V.size();
+    } else {
+        release_v(P.Xn);
+        release_w(P.WXn);
+        for (int i = 0; i < s.k; ++i) pos.push_back(i);
+    }
+    const int tpos = (int)P.Vb.size();
+    s.V.push_back(P.T);
+    s.W.push_back(P.TW);
+    pos.push_back(tpos);
+    const int kk = s.k;  // index of the new vector
+    for (int i = 0; i <= kk; ++i) s.G[i * nm + kk] = s.G[kk * nm + i] = r[sCol + pos[i]];
+    s.k = kk + 1;
+}
+
+}  // namespace tbsci
+
+using namespace tbsci;
+
+extern "C" {
+
+int tbsci_sigma_batch(tbsci_ctx *const *ctxs, int n, const void *const *C_dev,
+                      void *const *sigma_dev, int precision, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 0 || n > kBatchMaxSlots) throw Error(TBSCI_E_INVAL, "n must be in [0, 64]");
+        if (n == 0) return TBSCI_OK;
+        if (!ctxs || !C_dev || !sigma_dev) throw Error(TBSCI_E_INVAL, "NULL array");
+        if (precision != TBSCI_FP64 && precision != TBSCI_FP32)
+            throw Error(TBSCI_E_INVAL, "precision must be TBSCI_FP64 or TBSCI_FP32");
+        std::vector<Ctx *> cs(n);
+        for (int i = 0; i < n; ++i) {
+            check_ctx(ctxs[i]);
+            cs[i] = ctx_of(ctxs[i]);
+            if (cs[i]->device != cs[0]->device)
+                throw Error(TBSCI_E_INVAL, "contexts are on different devices");
+            check_dev(C_dev[i], cs[i]->device, "C");
+            check_dev(sigma_dev[i], cs[i]->device, "sigma");
+            if (C_dev[i] == sigma_dev[i]) throw Error(TBSCI_E_INVAL, "C and sigma must not alias");
+            for (int j = 0; j < i; ++j)
+                if (cs[j] == cs[i]) throw Error(TBSCI_E_INVAL, "a context appears twice");
+        }
+        TB_HIP(hipSetDevice(cs[0]->device));
+        for (Ctx *c : cs) reserve_sigma_workspace(*c);
+        TableArena ar(64u << 10);
+        hipStream_t st = (hipStream_t)stream;
+        launch_sigma_group(cs.data(), C_dev, sigma_dev, n, precision, ar, st);
+        TB_HIP(hipStreamSynchronize(st));
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_davidson_batch(tbsci_ctx *const *ctxs, int n, const tbsci_davidson_opts *opts,
+                         tbsci_davidson_info *infos, int *status, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 0 || n > kBatchMaxSlots) throw Error(TBSCI_E_INVAL, "n must be in [0, 64]");
+        if (n == 0) return TBSCI_OK;
+        if (!ctxs || !infos || !status) throw Error(TBSCI_E_INVAL, "NULL array");
+        std::vector<Ctx *> cs(n);
+        std::vector<tbsci_davidson_opts> os(n);
+        for (int i = 0; i < n; ++i) {
+            check_ctx(ctxs[i]);
+            cs[i] = ctx_of(ctxs[i]);
+            if (cs[i]->device != cs[0]->device)
+                throw Error(TBSCI_E_INVAL, "contexts are on different devices");
+            for (int j = 0; j < i; ++j)
+                if (cs[j] == cs[i]) throw Error(TBSCI_E_INVAL, "a context appears twice");
+            if (opts)
+                os[i] = opts[i];
+            else
+                tbsci_davidson_default_opts(&os[i]);
+            check_opts(os[i]);
+            if (os[i].n_max > kBatchMaxVec)
+                throw Error(TBSCI_E_INVAL, "n_max must be at most 16 in a batch");
+        }
+        TB_HIP(hipSetDevice(cs[0]->device));
+        hipStream_t st = (hipStream_t)stream;
+        std::vector<BatchSlot *> slots;
+        int rc = TBSCI_OK;
+        try {
+            BatchEngine eng(cs[0]->device, st);
+            const char *tr = getenv("TBSCI_DAVIDSON_TRACE");
+            eng.trace = tr && tr[0] && tr[0] != '0';
+            for (int i = 0; i < n; ++i) {
+                reserve_sigma_workspace(*cs[i]);
+                slots.push_back(BatchEngine::make_slot(cs[i], os[i]));
+                slots.back()->user = (void *)(intptr_t)i;
+                eng.add(slots.back());
+            }
+            while (eng.tick()) {
+            }
+            for (BatchSlot *s : eng.take_done()) {
+                const int i = (int)(intptr_t)s->user;
+                infos[i] = s->info;
+                status[i] = s->status;
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(st);
+            for (BatchSlot *s : slots) BatchEngine::free_slot(s);
+            throw;
+        }
+        for (BatchSlot *s : slots) BatchEngine::free_slot(s);
+        return rc;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Lock-step batched Davidson over several TPB problems on one device.
+//
+// Every active problem ("slot") advances one Davidson iteration per tick.
+// A tick issues each vector operation as ONE grouped launch over all slots
+// that need it, the sigma builds of all slots as one grouped launch per
+// kernel type (per precision), and ends with a single host synchronisation
+// that brings back every slot's k x k scalars.  Slots join and leave
+// between ticks, which is what the serving loop's continuous batching
+// builds on.
+//
+// The iteration is the one of the single-problem solver (same restart,
+// same mixed-precision hand-over), reorganised so that a tick needs one
+// synchronisation: the correction vector of a tick and its sigma are
+// computed before the host sees the residual of that tick's Ritz pair, so
+// the last tick of a converged slot builds one sigma that is discarded.
+// Reductions use a block count fixed by the slot's size, so the arithmetic
+// of a slot does not depend on which other slots share its launches.
+#pragma once
+
+#include <chrono>
+#include <vector>
+
+#include "tbsci_internal.hpp"
+
+namespace tbsci {
+
+constexpr int kBatchMaxVec = 16;  // largest n_max in a batch
+constexpr int kBatchMaxSlots = 64;
+
+struct BatchSlot {
+    Ctx *c = nullptr;
+    tbsci_davidson_opts o{};
+    int64_t n = 0;
+    int nb = 1;    // blocks of this slot in grid-stride launches
+    int row = -1;  // row of the scalar area while active
+    // device state: basis V / W (each from its pool of n_max + 3 vectors),
+    // the latest Ritz vector kept for a hand-over, FP32 staging, partials
+    std::vector<double *> all, vfree, wfree, V, W;
+    double *X = nullptr;
+    float *f32a = nullptr, *f32b = nullptr;
+    double *partial = nullptr;
+    size_t bytes = 0;  // device bytes of the above (page-rounded)
+    // host state
+    enum { kStart, kHandover, kIter, kDone } phase = kStart;
+    bool fp32 = false;
+    int k = 0;
+    std::vector<double> G, y, yprev;
+    double theta = 0.0, theta_prev = 0.0, rn = 1e300, best_rn = 1e300;
+    int since_best = 0;
+    int status = TBSCI_PENDING;
+    tbsci_davidson_info info{};
+    std::chrono::steady_clock::time_point t0;
+    void *user = nullptr;  // owner's tag
+    // plan of the current tick
+    struct Plan {
+        bool sig32 = false, restart = false, took_xp = false;
+        double *V0 = nullptr, *W0 = nullptr;           // start / hand-over
+        double *Xn = nullptr, *WXn = nullptr, *T = nullptr, *TW = nullptr;
+        double *XP = nullptr, *WXP = nullptr;
+        std::vector<double *> Vb, Wb;                  // basis the new vector joins
+    } p;
+};
+
+class BatchEngine {
+  public:
+    BatchEngine(int device, hipStream_t st);
+    ~BatchEngine();
+    BatchEngine(const BatchEngine &) = delete;
+    BatchEngine &operator=(const BatchEngine &) = delete;
+
+    // device bytes of a slot's solver state for n determinants
+    static size_t slot_bytes(int64_t n, const tbsci_davidson_opts &o);
+    // allocate a slot for context c (any thread; allocation only)
+    static BatchSlot *make_slot(Ctx *c, const tbsci_davidson_opts &o);
+    // free a slot's buffers (not its context); any thread, slot not active
+    static void free_slot(BatchSlot *s);
+
+    // the slot joins at the next tick (engine thread)
+    void add(BatchSlot *s);
+    size_t active() const { return act_.size(); }
+    // one iteration of every active slot; false if there was none
+    bool tick();
+    // slots finished since the last call
+    std::vector<BatchSlot *> take_done();
+    // remove every active slot unfinished (after the stream has drained)
+    std::vector<BatchSlot *> drain();
+
+    int64_t ticks = 0;
+    int max_group = 0;
+    bool trace = false;
+
+  private:
+    struct Stage;
+    void plan(BatchSlot &s, Stage &S);
+    void commit(BatchSlot &s, const double *r, double t_sig);
+    void finish(BatchSlot &s, double *keep);
+
+    int device_;
+    hipStream_t st_;
+    TableArena ar_;
+    double *scal_dev_ = nullptr, *scal_host_ = nullptr;
+    hipEvent_t ev_[2] = {nullptr, nullptr};
+    std::vector<BatchSlot *> act_, done_;
+    std::vector<int> free_rows_;
+};
+
+}  // namespace tbsci

@@ -139,10 +139,16 @@ __global__ __launch_bounds__(kB) void k_lincomb2(int64_t n, VecList V, VecList W
     }
 }
 
-__global__ void k_unit(int64_t n, int64_t at, double *__restrict__ v) {
+// v = e_at, or (e_at + e_at2) / sqrt(2) when at2 != at
+__global__ void k_unit(int64_t n, int64_t at, int64_t at2, double *__restrict__ v) {
+    const double val = at2 == at ? 1.0 : 0.70710678118654752440;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x)
-        v[x] = x == at ? 1.0 : 0.0;
+        v[x] = (x == at || x == at2) ? val : 0.0;
+}
+
+__global__ __launch_bounds__(kB) void k_flip_sym(int64_t l, double *__restrict__ T) {
+    flip_sym_block(blockIdx.x, l, T);
 }
 
 __global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
@@ -198,6 +204,8 @@ __global__ void k_scale_const(int64_t n, double s, double *__restrict__ v) {
         v[x] *= s;
 }
 
+}  // namespace
+
 // Cyclic Jacobi on a symmetric k x k matrix: eigenvalues w, eigenvectors
 // in the columns of Z (row-major k x k).
 void jacobi_eigh(int k, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z) {
@@ -240,6 +248,8 @@ void jacobi_eigh(int k, std::vector<double> A, std::vector<double> &w, std::vect
     for (int i = 0; i < k; ++i) w[i] = A[i * k + i];
 }
 
+namespace {
+
 struct Workspace {
     std::vector<double *> bufs;
     ~Workspace() {
@@ -269,8 +279,17 @@ struct Events {
 }  // namespace
 
 // Shared by the serving engine: one solve on an existing context.
+size_t davidson_bytes(int64_t n, const tbsci_davidson_opts &o) {
+    auto page = [](size_t b) { return (std::max<size_t>(b, 8) + 4095) & ~size_t(4095); };
+    size_t b = (size_t)(2 * o.n_max + 5) * page(8 * (size_t)n);
+    if (o.precision == TBSCI_MIXED) b += 2 * page(8 * (size_t)((n + 1) / 2));
+    b += page(8 * (size_t)kMaxVec * kRedBlocks) + 2 * page(8 * (size_t)kMaxVec) +
+         page(8 * (size_t)kRedBlocks);
+    return b;
+}
+
 int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *C_out,
-                 tbsci_davidson_info &info, hipStream_t st) {
+                 tbsci_davidson_info &info, hipStream_t st, const std::atomic<bool> *abort) {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t la = c.sp[0].l, lb = c.sp[1].l, n = la * lb;
     const int nmax = o.n_max;
@@ -296,6 +315,10 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
     Events ev;
 
     memset(&info, 0, sizeof(info));
+    // flip-symmetric space and no guess: the solve is kept in the C = C^T
+    // sector (start vector symmetric, every correction symmetrised), so that
+    // rounding in the sigma build cannot carry it into the other sector
+    const bool sym = c.flip && !guess;
     const char *tr_env = getenv("TBSCI_DAVIDSON_TRACE");  // per-iteration trace on stderr
     const bool trace = tr_env && tr_env[0] && tr_env[0] != '0';
     double t_sigma = 0.0;
@@ -356,7 +379,11 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
                 best = pv[b];
                 at = pi[b];
             }
-        k_unit<<<1024, kB, 0, st>>>(n, at, V[0]);
+        // in a flip-symmetric space an open-shell start |I J> becomes
+        // (|I J> + |J I>) / sqrt(2), so the solve stays in the C = C^T sector
+        const int64_t ia = at / lb, ib = at - ia * lb;
+        const int64_t at2 = c.flip ? ib * lb + ia : at;
+        k_unit<<<1024, kB, 0, st>>>(n, at, at2, V[0]);
     }
     TB_HIP(hipGetLastError());
 
@@ -367,7 +394,7 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
     G[0] = col[0];
     double theta = 0.0, theta_prev = 0.0, rn = 1e300, best_rn = 1e300;
     int since_best = 0;
-    bool done = false, converged = false;
+    bool done = false, converged = false, force_fp64 = false;
     while (!done) {
         std::vector<double> Gk((size_t)k * k);
         for (int i = 0; i < k; ++i)
@@ -388,6 +415,10 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
                                   c.sp[0].str, c.sp[0].dsame, c.sp[1].dsame, c.sp[1].jocc, X, WX, T,
                                   partial);
         k_reduce<<<1, kB, 0, st>>>(partial, gb, dots);
+        if (sym) {
+            const int64_t nt = (lb + 31) / 32;
+            k_flip_sym<<<(unsigned)(nt * nt), kB, 0, st>>>(lb, T);
+        }
         double r2;
         TB_HIP(hipMemcpyAsync(&r2, dots, sizeof(double), hipMemcpyDeviceToHost, st));
         TB_HIP(hipStreamSynchronize(st));
@@ -408,7 +439,7 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
                 ++since_best;
             }
             const bool at_floor = rn < 10.0 * 2e-6 * std::fabs(theta);
-            if (rn <= o.fp32_switch_resid || (since_best >= 20 && at_floor) ||
+            if (rn <= o.fp32_switch_resid || (since_best >= 20 && at_floor) || force_fp64 ||
                 info.iters >= o.max_iter / 2) {
                 // correction phase: restart from the Ritz vector with FP64 sigma builds
                 fp32 = false;
@@ -427,6 +458,12 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
             break;
         }
         if (info.iters >= o.max_iter) break;
+        if (abort && abort->load()) {
+            info.energy = theta;
+            info.resid_norm = rn;
+            info.converged = 0;
+            return TBSCI_E_STATE;
+        }
         if (k >= nmax) {
             // restart: keep the Ritz vector x = V y and the part of the
             // previous Ritz vector orthogonal to it, z = yp - (yp.y) y
@@ -441,7 +478,7 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
             std::swap(V[0], X);
             std::swap(W[0], WX);
             bool two = false;
-            if (nz > 1e-8) {
+            if (nz > 1e-8 && nmax >= 3) {  // room for x, the previous direction and t
                 for (int i = 0; i < k; ++i) z[i] /= nz;
                 TB_HIP(hipMemcpyAsync(ydev, z.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
                 // X / WX now hold the old V[0] / W[0]: V and W of the old basis
@@ -505,8 +542,7 @@ int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, doub
         multidot(tv, 1, T, &tn2);
         if (!(std::sqrt(std::max(tn2, 0.0)) >= 1e-10)) {
             if (fp32) {  // no new direction in FP32: go to the FP64 phase
-                best_rn = 0.0;
-                since_best = 1000;
+                force_fp64 = true;
                 continue;
             }
             break;  // stagnation

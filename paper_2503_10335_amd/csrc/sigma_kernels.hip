@@ -52,13 +52,12 @@ struct Vals<float> {
 // and an XCD walks its tiles one after the other, so its working set is one
 // panel of X (nrows x 64 columns).
 template <typename T, bool ACC>
-__global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t ncols, int64_t ntiles,
-                                                      int64_t nrb, int64_t tiles_per_xcd,
-                                                      const int64_t *__restrict__ ptr,
-                                                      const int32_t *__restrict__ col,
-                                                      const T *__restrict__ val,
-                                                      const T *__restrict__ X, T *__restrict__ Y) {
-    const int64_t b = blockIdx.x;
+__device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_t ncols,
+                                                int64_t ntiles, int64_t nrb, int64_t tiles_per_xcd,
+                                                const int64_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ col,
+                                                const T *__restrict__ val,
+                                                const T *__restrict__ X, T *__restrict__ Y) {
     const int64_t xcd = b % kXcd, local = b / kXcd;
     const int64_t tl = local / nrb, rb = local - tl * nrb;
     const int64_t tile = xcd + kXcd * tl;
@@ -102,12 +101,55 @@ __global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t nco
     }
 }
 
+template <typename T, bool ACC>
+__global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t ncols, int64_t ntiles,
+                                                      int64_t nrb, int64_t tiles_per_xcd,
+                                                      const int64_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val,
+                                                      const T *__restrict__ X, T *__restrict__ Y) {
+    row_sweep_block<T, ACC>(blockIdx.x, nrows, ncols, ntiles, nrb, tiles_per_xcd, ptr, col, val, X,
+                            Y);
+}
+
+// Descriptor of one problem in a grouped launch; the problem's blocks are
+// [blk0, blk0 + its block count), blk0 a multiple of 8 so that the XCD of a
+// block is the same as in a launch of its own.
+struct SweepDesc {
+    int64_t blk0, nrows, ncols, ntiles, nrb, tpx;
+    const int64_t *ptr;
+    const int32_t *col;
+    const void *val, *X;
+    void *Y;
+};
+
+// index of the descriptor whose block range holds block b (blk0 ascending)
+template <typename D>
+__device__ __forceinline__ int find_desc(const D *__restrict__ d, int nd, int64_t b) {
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].blk0 <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, bool ACC>
+__global__ __launch_bounds__(kBlock) void g_row_sweep(const SweepDesc *__restrict__ d, int nd) {
+    const SweepDesc &e = d[find_desc(d, nd, blockIdx.x)];
+    row_sweep_block<T, ACC>(blockIdx.x - e.blk0, e.nrows, e.ncols, e.ntiles, e.nrb, e.tpx, e.ptr,
+                            e.col, (const T *)e.val, (const T *)e.X, (T *)e.Y);
+}
+
 // out[c][r] (+)= in[r][c] for an R x Cn row-major input; 32 x 32 tiles via LDS.
 template <typename T, bool ADD>
-__global__ __launch_bounds__(kBlock) void k_transpose(int64_t R, int64_t Cn, int64_t ntc,
-                                                      const T *__restrict__ in, T *__restrict__ out) {
+__device__ __forceinline__ void transpose_block(int64_t b, int64_t R, int64_t Cn, int64_t ntc,
+                                                const T *__restrict__ in, T *__restrict__ out) {
     __shared__ T tile[32][33];
-    const int64_t tr = blockIdx.x / ntc, tc = blockIdx.x - tr * ntc;
+    const int64_t tr = b / ntc, tc = b - tr * ntc;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
     for (int i = ty; i < 32; i += 8) {
@@ -126,6 +168,24 @@ __global__ __launch_bounds__(kBlock) void k_transpose(int64_t R, int64_t Cn, int
                 out[c * R + r] = v;
         }
     }
+}
+
+template <typename T, bool ADD>
+__global__ __launch_bounds__(kBlock) void k_transpose(int64_t R, int64_t Cn, int64_t ntc,
+                                                      const T *__restrict__ in, T *__restrict__ out) {
+    transpose_block<T, ADD>(blockIdx.x, R, Cn, ntc, in, out);
+}
+
+struct TransDesc {
+    int64_t blk0, R, Cn, ntc;
+    const void *in;
+    void *out;
+};
+
+template <typename T, bool ADD>
+__global__ __launch_bounds__(kBlock) void g_transpose(const TransDesc *__restrict__ d, int nd) {
+    const TransDesc &e = d[find_desc(d, nd, blockIdx.x)];
+    transpose_block<T, ADD>(blockIdx.x - e.blk0, e.R, e.Cn, e.ntc, (const T *)e.in, (T *)e.out);
 }
 
 // ---------------------------------------------------------- opposite spin
@@ -218,15 +278,15 @@ inline AbLds ab_lds(int64_t lb, int kmax, size_t sz, size_t row_sz) {
     return L;
 }
 
-template <typename T, int KS, int ROW, int BOUND>
-__global__ __launch_bounds__(BOUND) void k_ab_tile(int64_t lb, int P, int nmt, AbLds L,
-                                                  const int64_t *__restrict__ sa_ptr,
-                                                  const Ent *__restrict__ sa_ent,
-                                                  const int64_t *__restrict__ sb_ptr,
-                                                  const Ent *__restrict__ sb_grp,
-                                                  const int32_t *__restrict__ sb_off,
-                                                  const T *__restrict__ V, const T *__restrict__ C,
-                                                  T *__restrict__ S) {
+template <typename T, int KS, int ROW>
+__device__ __forceinline__ void ab_tile_row(const int64_t I, int64_t lb, int P, int nmt,
+                                            const AbLds &L, const int64_t *__restrict__ sa_ptr,
+                                            const Ent *__restrict__ sa_ent,
+                                            const int64_t *__restrict__ sb_ptr,
+                                            const Ent *__restrict__ sb_grp,
+                                            const int32_t *__restrict__ sb_off,
+                                            const T *__restrict__ V, const T *__restrict__ C,
+                                            T *__restrict__ S) {
     using M = Mfma<T>;
     using R = typename std::conditional<ROW == kRowF64, double, T>::type;
     constexpr bool LDS_ROW = ROW != kRowGlobal;
@@ -235,7 +295,6 @@ __global__ __launch_bounds__(BOUND) void k_ab_tile(int64_t lb, int P, int nmt, A
     int32_t *aj = (int32_t *)(smem + L.aj);
     T *xbuf = (T *)(smem + L.x);
 
-    const int64_t I = blockIdx.x;
     const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, cl = lane & 15;
@@ -361,6 +420,40 @@ __global__ __launch_bounds__(BOUND) void k_ab_tile(int64_t lb, int P, int nmt, A
     }
     if (LDS_ROW)
         for (int64_t i = tid; i < lb; i += nthr) S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
+}
+
+template <typename T, int KS, int ROW, int BOUND>
+__global__ __launch_bounds__(BOUND) void k_ab_tile(int64_t lb, int P, int nmt, AbLds L,
+                                                  const int64_t *__restrict__ sa_ptr,
+                                                  const Ent *__restrict__ sa_ent,
+                                                  const int64_t *__restrict__ sb_ptr,
+                                                  const Ent *__restrict__ sb_grp,
+                                                  const int32_t *__restrict__ sb_off,
+                                                  const T *__restrict__ V, const T *__restrict__ C,
+                                                  T *__restrict__ S) {
+    ab_tile_row<T, KS, ROW>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off, V,
+                            C, S);
+}
+
+// one problem of a grouped opposite-spin launch: blocks [blk0, blk0 + l_alpha)
+struct AbDesc {
+    int64_t blk0, lb;
+    AbLds L;
+    const int64_t *sa_ptr;
+    const Ent *sa_ent;
+    const int64_t *sb_ptr;
+    const Ent *sb_grp;
+    const int32_t *sb_off;
+    const void *V, *C;
+    void *S;
+};
+
+template <typename T, int KS, int ROW, int BOUND>
+__global__ __launch_bounds__(BOUND) void g_ab_tile(const AbDesc *__restrict__ d, int nd, int P,
+                                                  int nmt) {
+    const AbDesc &e = d[find_desc(d, nd, blockIdx.x)];
+    ab_tile_row<T, KS, ROW>(blockIdx.x - e.blk0, e.lb, P, nmt, e.L, e.sa_ptr, e.sa_ent, e.sb_ptr,
+                            e.sb_grp, e.sb_off, (const T *)e.V, (const T *)e.C, (T *)e.S);
 }
 
 // ---------------------------------------------------------------- driver
@@ -521,7 +614,136 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms) {
     timing_mark(c, 3, prec, st);
 }
 
+// KS instance used by the tile kernel for a context (0: direct kernel)
+int ab_ks(const Ctx &c) {
+    const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
+    const int nmt = (c.P + 15) / 16;
+    if (ks > 32 || nmt > 16 || 4 * ks * kTW > kXPT * 64 * nmt) return 0;
+    return (ks + 3) / 4 * 4;
+}
+
+template <typename T, int KS, int BOUND>
+void launch_ab_group_kb(const AbDesc *dd, int nd, int64_t blocks, int P, size_t lds, Ctx &c0,
+                        hipStream_t st) {
+    const int nmt = (P + 15) / 16;
+    auto f = g_ab_tile<T, KS, kRowF64, BOUND>;
+    if (lds > 64 * 1024) allow_lds(c0, (const void *)f, lds);
+    f<<<(unsigned)blocks, 64 * nmt, lds, st>>>(dd, nd, P, nmt);
+    TB_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_ab_group(const AbDesc *dd, int nd, int64_t blocks, int P, int KS, size_t lds, Ctx &c0,
+                     hipStream_t st) {
+    const bool small = (P + 15) / 16 <= 10;
+#define TB_G(n)                                                                      \
+    case n:                                                                          \
+        if (small)                                                                   \
+            launch_ab_group_kb<T, n, 640>(dd, nd, blocks, P, lds, c0, st);           \
+        else                                                                         \
+            launch_ab_group_kb<T, n, 1024>(dd, nd, blocks, P, lds, c0, st);          \
+        break;
+    switch (KS) {
+        TB_G(4) TB_G(8) TB_G(12) TB_G(16) TB_G(20) TB_G(24) TB_G(28) TB_G(32)
+        default:
+            throw Error(TBSCI_E_DEVICE, "no grouped opposite-spin kernel for this shape");
+    }
+#undef TB_G
+}
+
+template <typename T>
+void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, TableArena &ar,
+                      hipStream_t st) {
+    std::vector<SweepDesc> sa, sb;
+    std::vector<TransDesc> t1, t2;
+    int64_t bsa = 0, bsb = 0, bt1 = 0, bt2 = 0;
+    auto sweep = [&](std::vector<SweepDesc> &v, int64_t &blk, const Spin &s, int64_t ncols,
+                     const T *X, T *Y) {
+        const int64_t ntiles = (ncols + 63) / 64, nrb = (s.l + 3) / 4;
+        const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
+        v.push_back(SweepDesc{blk, s.l, ncols, ntiles, nrb, tpx, s.a_ptr, s.a_col, Vals<T>::a(s),
+                              X, Y});
+        blk += kXcd * tpx * nrb;  // a multiple of 8
+    };
+    auto trans = [&](std::vector<TransDesc> &v, int64_t &blk, int64_t R, int64_t Cn, const T *in,
+                     T *out) {
+        const int64_t ntr = (R + 31) / 32, ntc = (Cn + 31) / 32;
+        v.push_back(TransDesc{blk, R, Cn, ntc, in, out});
+        blk += ntr * ntc;
+    };
+    // opposite-spin groups: problems with the same P and KS share a launch
+    struct Group {
+        int P, KS;
+        size_t lds;
+        int64_t blocks;
+        std::vector<AbDesc> d;
+    };
+    std::vector<Group> groups;
+    std::vector<int> direct;
+    for (int i = 0; i < n; ++i) {
+        Ctx &c = *ctx[i];
+        const Spin &A = c.sp[0], &B = c.sp[1];
+        T *Ct = workspace<T>(c, 0), *St = workspace<T>(c, 1);
+        sweep(sa, bsa, A, B.l, C[i], S[i]);
+        trans(t1, bt1, A.l, B.l, C[i], Ct);
+        sweep(sb, bsb, B, A.l, Ct, St);
+        trans(t2, bt2, B.l, A.l, St, S[i]);
+        const int KS = ab_ks(c);
+        const AbLds L = ab_lds(B.l, 4 * std::max(KS, 1), sizeof(T), 8);
+        if (KS == 0 || L.total > kLdsMax) {
+            direct.push_back(i);
+            continue;
+        }
+        Group *g = nullptr;
+        for (auto &x : groups)
+            if (x.P == c.P && x.KS == KS) g = &x;
+        if (!g) {
+            groups.push_back(Group{c.P, KS, 0, 0, {}});
+            g = &groups.back();
+        }
+        g->d.push_back(AbDesc{g->blocks, B.l, L, A.s_ptr, A.s_ent, B.s_ptr, B.g_ent, B.g_off,
+                              Vals<T>::V(c), C[i], S[i]});
+        g->blocks += A.l;
+        g->lds = std::max(g->lds, L.total);
+    }
+    if (n == 0) return;
+    const SweepDesc *dsa = ar.stage(sa.data(), sa.size());
+    const SweepDesc *dsb = ar.stage(sb.data(), sb.size());
+    const TransDesc *dt1 = ar.stage(t1.data(), t1.size());
+    const TransDesc *dt2 = ar.stage(t2.data(), t2.size());
+    std::vector<const AbDesc *> dg;
+    for (auto &g : groups) dg.push_back(ar.stage(g.d.data(), g.d.size()));
+    ar.flush(st);
+    g_row_sweep<T, false><<<(unsigned)bsa, kBlock, 0, st>>>(dsa, n);  // sigma = A_a C
+    g_transpose<T, false><<<(unsigned)bt1, kBlock, 0, st>>>(dt1, n);
+    g_row_sweep<T, false><<<(unsigned)bsb, kBlock, 0, st>>>(dsb, n);
+    g_transpose<T, true><<<(unsigned)bt2, kBlock, 0, st>>>(dt2, n);  // sigma += (A_b C^T)^T
+    TB_HIP(hipGetLastError());
+    for (size_t k = 0; k < groups.size(); ++k)
+        launch_ab_group<T>(dg[k], (int)groups[k].d.size(), groups[k].blocks, groups[k].P,
+                           groups[k].KS, groups[k].lds, *ctx[0], st);
+    for (int i : direct) {
+        Ctx &c = *ctx[i];
+        const Spin &A = c.sp[0], &B = c.sp[1];
+        const int64_t ncb = (B.l + kBlock - 1) / kBlock;
+        k_ab_direct<T><<<(unsigned)(A.l * ncb), kBlock, 0, st>>>(B.l, ncb, c.P, A.s_ptr, A.s_ent,
+                                                                  B.s_ptr, B.s_ent, Vals<T>::V(c),
+                                                                  C[i], S[i]);
+        TB_HIP(hipGetLastError());
+    }
+}
+
 }  // namespace
+
+void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, int n,
+                        int precision, TableArena &ar, hipStream_t st) {
+    if (precision == TBSCI_FP64)
+        sigma_group_impl<double>(ctx, (const double *const *)C, (double *const *)S, n, ar, st);
+    else
+        sigma_group_impl<float>(ctx, (const float *const *)C, (float *const *)S, n, ar, st);
+}
+
+void reserve_sigma_workspace(Ctx &c) { (void)workspace<double>(c, 0); }
 
 void timing_mark(Ctx &c, int index, int precision, hipStream_t st) {
     if (!c.timing) return;

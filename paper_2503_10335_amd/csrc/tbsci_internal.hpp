@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -68,6 +70,10 @@ struct Spin {
 
 struct Ctx {
     int M = 0, P = 0, device = 0;
+    // alpha and beta lists are the same strings in the same order with
+    // N_alpha = N_beta: H commutes with the spin flip C -> C^T (up to the
+    // sign (-1)^N), and the solvers start in the C = C^T sector
+    bool flip = false;
     double *h = nullptr;     // [M][M]
     double *eri = nullptr;   // [M^4]
     double *V64 = nullptr;   // folded [P][P]: V[pair(p,q)][pair(r,s)] = (pq|rs)
@@ -85,6 +91,49 @@ struct Ctx {
     std::vector<TimedCall> timed;
     // kernels whose dynamic LDS limit has been raised (kernel, bytes)
     std::vector<std::pair<const void *, size_t>> lds_set;
+};
+
+// Descriptor tables of grouped launches: an append-only region of pinned
+// host memory mirrored in device memory.  put() copies a table into the
+// host region and enqueues its transfer on the stream; the tables of one
+// round of launches stay valid until reset(), which the owner calls only
+// after the stream has drained.
+struct TableArena {
+    unsigned char *host = nullptr, *dev = nullptr;
+    size_t cap = 0, off = 0;
+    explicit TableArena(size_t bytes) : cap(bytes) {
+        TB_HIP(hipHostMalloc((void **)&host, cap, hipHostMallocDefault));
+        if (hipMalloc((void **)&dev, cap) != hipSuccess) {
+            (void)hipHostFree(host);
+            host = nullptr;
+            throw Error(TBSCI_E_NOMEM, "descriptor table allocation failed");
+        }
+    }
+    ~TableArena() {
+        if (dev) (void)hipFree(dev);
+        if (host) (void)hipHostFree(host);
+    }
+    TableArena(const TableArena &) = delete;
+    TableArena &operator=(const TableArena &) = delete;
+    // copy a table into the host region; its device copy is made by flush()
+    template <typename D>
+    const D *stage(const D *src, size_t n) {
+        const size_t bytes = n * sizeof(D), at = off;
+        if (bytes == 0) return nullptr;
+        if (at + bytes > cap) throw Error(TBSCI_E_NOMEM, "descriptor tables exceed their arena");
+        memcpy(host + at, src, bytes);
+        off = (at + bytes + 255) & ~size_t(255);
+        return (const D *)(dev + at);
+    }
+    // enqueue one transfer of everything staged since the last flush
+    void flush(hipStream_t st) {
+        if (off > flushed)
+            TB_HIP(hipMemcpyAsync(dev + flushed, host + flushed, off - flushed,
+                                  hipMemcpyHostToDevice, st));
+        flushed = off;
+    }
+    void reset() { off = flushed = 0; }
+    size_t flushed = 0;
 };
 
 // records an event on st if timing is on; index 0..TBSCI_N_KERNELS
@@ -112,6 +161,23 @@ int guarded(F &&f) {
     }
 }
 
+// ---- api.hip
+// validation of a problem (throws TBSCI_E_INVAL with a message)
+void validate_problem(int M, int n_alpha, int n_beta, const double *h, const double *eri,
+                      const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta,
+                      int64_t l_beta);
+void check_device_index(int device);
+// a context of validated inputs (synchronous; throws on device errors)
+Ctx *create_ctx(int M, int n_alpha, int n_beta, const double *h, const double *eri,
+                const uint64_t *alpha, int64_t l_alpha, const uint64_t *beta, int64_t l_beta,
+                int device);
+void destroy_ctx(Ctx *c);
+// device bytes a context holds (page-rounded allocation sizes, sigma
+// workspace included), and an upper bound of it, transients of the list
+// build included, from the problem shape alone
+size_t ctx_bytes(const Ctx &c);
+size_t ctx_bytes_bound(int M, int n_alpha, int n_beta, int64_t l_alpha, int64_t l_beta);
+
 Ctx *ctx_of(const tbsci_ctx *p);
 void check_ctx(const tbsci_ctx *ctx);
 void check_dev(const void *p, int device, const char *name);
@@ -125,10 +191,46 @@ void launch_diag_argmin(const Ctx &c, double *part_val, int64_t *part_idx, int n
 // ---- launchers (sigma_kernels.hip)
 void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms = 7);
 double executed_flops(Ctx &c, int kernel, int precision);
+// sigma of n problems in shared launches (one per kernel type, the
+// opposite-spin term one per group of equal tile shape); C[i], S[i] are
+// device arrays of precision `precision` for ctx[i].  Tables go to `ar`.
+void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, int n,
+                        int precision, TableArena &ar, hipStream_t st);
+// make sure the sigma workspace of c exists (allocates)
+void reserve_sigma_workspace(Ctx &c);
 
 // ---- davidson.hip
+// T = (T + T^T) / 2 in place for a square l x l row-major matrix, one
+// 256-thread block per 32 x 32 tile pair (bi <= bj; blocks with bi > bj
+// return); used on correction vectors to keep a flip-symmetric solve in
+// the C = C^T sector
+__device__ __forceinline__ void flip_sym_block(int64_t b, int64_t l, double *__restrict__ T) {
+    __shared__ double A[32][33], B[32][33];
+    const int64_t nt = (l + 31) / 32, bi = b / nt, bj = b - bi * nt;
+    if (bi > bj) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+        A[r][tx] = (i < l && j < l) ? T[i * l + j] : 0.0;
+        const int64_t i2 = bj * 32 + r, j2 = bi * 32 + tx;
+        B[r][tx] = (i2 < l && j2 < l) ? T[i2 * l + j2] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < l && j < l) T[i * l + j] = 0.5 * (A[r][tx] + B[tx][r]);
+        const int64_t i2 = bj * 32 + r, j2 = bi * 32 + tx;
+        if (i2 < l && j2 < l) T[i2 * l + j2] = 0.5 * (B[r][tx] + A[tx][r]);
+    }
+}
+
+// abort (optional): checked once per iteration; a set flag ends the solve
+// with TBSCI_E_STATE
 int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *C_out,
-                 tbsci_davidson_info &info, hipStream_t st);
+                 tbsci_davidson_info &info, hipStream_t st,
+                 const std::atomic<bool> *abort = nullptr);
+// device bytes davidson_run allocates for n determinants
+size_t davidson_bytes(int64_t n, const tbsci_davidson_opts &o);
 void check_opts(const tbsci_davidson_opts &o);
 
 }  // namespace tbsci

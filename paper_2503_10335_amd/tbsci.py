@@ -45,6 +45,18 @@ class DavidsonOpts(ctypes.Structure):
                 ("fp32_switch_resid", ctypes.c_double), ("precond_floor", ctypes.c_double)]
 
 
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("hbm_reserved", ctypes.c_size_t),
+                ("hbm_reserved_peak", ctypes.c_size_t), ("submitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("running_batched", ctypes.c_int64),
+                ("running_solo", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("max_batch", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class DavidsonInfo(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("resid_norm", ctypes.c_double),
                 ("iters", ctypes.c_int), ("iters_fp32", ctypes.c_int), ("iters_fp64", ctypes.c_int),
@@ -83,6 +95,14 @@ def load():
         "tbsci_timing_enable": (c_int, [P, c_int]),
         "tbsci_timing_read": (c_int, [P, c_int, c_int, P, P, P, P, P]),
         "tbsci_timing_executed_flops": (c_int, [P, c_int, c_int, P]),
+        "tbsci_sigma_batch": (c_int, [P, c_int, P, P, c_int, P]),
+        "tbsci_davidson_batch": (c_int, [P, c_int, P, P, P, P]),
+        "tbsci_server_create": (c_int, [c_int, ctypes.c_size_t, i64, P]),
+        "tbsci_server_destroy": (None, [P]),
+        "tbsci_submit": (c_int, [P, c_int, c_int, c_int, P, P, P, i64, P, i64, P, P]),
+        "tbsci_poll": (c_int, [P, ctypes.c_uint64, P]),
+        "tbsci_request_times": (c_int, [P, ctypes.c_uint64, P, P, P, P]),
+        "tbsci_server_stats": (c_int, [P, P]),
         "tbsci_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -226,6 +246,127 @@ def tbsci_timing_executed_flops(ctx, kernel, precision=TBSCI_FP64):
     return fl.value
 
 
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * max(len(ptrs), 1))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p
+    return arr
+
+
+def tbsci_sigma_batch(ctxs, Cs, Ss, precision=TBSCI_FP64, stream=None):
+    n = len(ctxs)
+    _check(load().tbsci_sigma_batch(_ptr_array([c.value for c in ctxs]), n,
+                                    _ptr_array([C.data_ptr() for C in Cs]),
+                                    _ptr_array([S.data_ptr() for S in Ss]), int(precision),
+                                    _stream(stream)))
+
+
+def tbsci_davidson_batch(ctxs, opts=None, stream=None):
+    n = len(ctxs)
+    infos = (DavidsonInfo * max(n, 1))()
+    status = (ctypes.c_int * max(n, 1))()
+    op = None
+    if opts is not None:
+        op = (DavidsonOpts * n)(*opts)
+    _check(load().tbsci_davidson_batch(_ptr_array([c.value for c in ctxs]), n, op, infos, status,
+                                       _stream(stream)))
+    return [status[i] for i in range(n)], [infos[i] for i in range(n)]
+
+
+def tbsci_server_create(device=0, hbm_budget_bytes=64 << 30, batch_ndet_threshold=2_000_000):
+    out = ctypes.c_void_p()
+    _check(load().tbsci_server_create(int(device), int(hbm_budget_bytes),
+                                      int(batch_ndet_threshold), ctypes.byref(out)))
+    return out
+
+
+def tbsci_server_destroy(srv):
+    load().tbsci_server_destroy(srv)
+
+
+def tbsci_submit(srv, M, n_alpha, n_beta, h, eri, alpha, beta, opts=None):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    a = np.ascontiguousarray(alpha, dtype=np.uint64)
+    b = np.ascontiguousarray(beta, dtype=np.uint64)
+    t = ctypes.c_uint64()
+    _check(load().tbsci_submit(srv, int(M), int(n_alpha), int(n_beta), _np_ptr(h), _np_ptr(eri),
+                               _np_ptr(a), len(a), _np_ptr(b), len(b),
+                               ctypes.byref(opts) if opts is not None else None, ctypes.byref(t)))
+    return t.value
+
+
+def tbsci_poll(srv, ticket):
+    """(status, info): status TBSCI_PENDING while not finished."""
+    info = DavidsonInfo()
+    rc = load().tbsci_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(info))
+    if rc == TBSCI_E_NOTFOUND:
+        raise TbsciError(rc, last_error())
+    return rc, info
+
+
+def tbsci_request_times(srv, ticket):
+    q, lat = ctypes.c_double(), ctypes.c_double()
+    bt, fp = ctypes.c_int(), ctypes.c_int64()
+    rc = load().tbsci_request_times(srv, ctypes.c_uint64(ticket), ctypes.byref(q),
+                                    ctypes.byref(lat), ctypes.byref(bt), ctypes.byref(fp))
+    _check(rc, allow=(TBSCI_OK, TBSCI_PENDING))
+    if rc == TBSCI_PENDING:
+        return None
+    return dict(queue_s=q.value, latency_s=lat.value, batched=bool(bt.value),
+                footprint_bytes=fp.value)
+
+
+def tbsci_server_stats(srv):
+    s = ServerInfo()
+    _check(load().tbsci_server_stats(srv, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def make_opts(n_max=8, max_iter=200, precision=TBSCI_FP64, tol_resid=1e-6, tol_energy=0.0,
+              fp32_switch_resid=1e-4, precond_floor=1e-8):
+    o = tbsci_davidson_default_opts()
+    o.n_max, o.max_iter, o.precision = n_max, max_iter, precision
+    o.tol_resid, o.tol_energy = tol_resid, tol_energy
+    o.fp32_switch_resid, o.precond_floor = fp32_switch_resid, precond_floor
+    return o
+
+
+class Server:
+    """Serving loop on one device (tbsci_server_*)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=64 << 30, batch_ndet_threshold=2_000_000):
+        self._srv = tbsci_server_create(device, hbm_budget_bytes, batch_ndet_threshold)
+
+    def submit(self, prob, **opts):
+        o = make_opts(**opts) if opts else None
+        return tbsci_submit(self._srv, prob.M, prob.n_alpha, prob.n_beta, prob.h, prob.eri,
+                            prob.alpha, prob.beta, o)
+
+    def poll(self, ticket):
+        rc, info = tbsci_poll(self._srv, ticket)
+        if rc == TBSCI_PENDING:
+            return None
+        d = info.as_dict()
+        d["status"] = rc
+        d.update(tbsci_request_times(self._srv, ticket))
+        return d
+
+    def stats(self):
+        return tbsci_server_stats(self._srv)
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            tbsci_server_destroy(self._srv)
+            self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---------------------------------------------------------------- wrapper
 
 class Context:
@@ -292,10 +433,8 @@ class Context:
     def davidson(self, n_max=8, max_iter=200, precision=TBSCI_FP64, tol_resid=1e-6,
                  tol_energy=0.0, fp32_switch_resid=1e-4, precond_floor=1e-8, guess=None,
                  want_vector=True, stream=None):
-        o = tbsci_davidson_default_opts()
-        o.n_max, o.max_iter, o.precision = n_max, max_iter, precision
-        o.tol_resid, o.tol_energy = tol_resid, tol_energy
-        o.fp32_switch_resid, o.precond_floor = fp32_switch_resid, precond_floor
+        o = make_opts(n_max, max_iter, precision, tol_resid, tol_energy, fp32_switch_resid,
+                      precond_floor)
         if guess is not None and (guess.dtype != torch.float64 or guess.numel() != self.n_det):
             raise ValueError("guess must be an FP64 device tensor of n_det elements")
         X = torch.empty((self.l_alpha, self.l_beta), dtype=torch.float64,
@@ -315,3 +454,27 @@ class Context:
 
     def get_list(self, spin, kind):
         return tbsci_get_list(self._ctx, spin, kind, self.l_alpha if spin == 0 else self.l_beta)
+
+
+def sigma_batch(contexts, Cs, precision=TBSCI_FP64, stream=None):
+    """sigma of several contexts in shared launches; returns new tensors."""
+    dt = torch.float64 if precision == TBSCI_FP64 else torch.float32
+    outs = []
+    for c, C in zip(contexts, Cs):
+        if C.dtype != dt or not C.is_cuda or not C.is_contiguous() or C.numel() != c.n_det:
+            raise ValueError("each C must be a contiguous device tensor of its n_det elements")
+        outs.append(torch.empty((c.l_alpha, c.l_beta), dtype=dt, device=C.device))
+    tbsci_sigma_batch([c.handle for c in contexts], Cs, outs, precision, stream)
+    return outs
+
+
+def davidson_batch(contexts, stream=None, **opts):
+    """Lowest eigenvalues of several contexts solved in lock step."""
+    o = [make_opts(**opts) for _ in contexts]
+    status, infos = tbsci_davidson_batch([c.handle for c in contexts], o, stream)
+    out = []
+    for st, inf in zip(status, infos):
+        d = inf.as_dict()
+        d["status"] = st
+        out.append(d)
+    return out

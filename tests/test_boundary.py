@@ -92,3 +92,31 @@ def test_null_handles_are_safe(T):
     o = T.tbsci_davidson_default_opts()
     assert (o.n_max, o.max_iter, o.precision) == (8, 200, T.TBSCI_FP64)
     assert o.tol_resid == 1e-6 and o.fp32_switch_resid == 1e-4
+
+
+def test_batch_and_server_null_and_invalid(T, good):
+    lib = T.load()
+    lib.tbsci_server_destroy(None)
+    info = T.DavidsonInfo()
+    assert lib.tbsci_poll(None, 1, ctypes.byref(info)) == T.TBSCI_E_INVAL
+    assert lib.tbsci_server_stats(None, None) == T.TBSCI_E_INVAL
+    assert lib.tbsci_request_times(None, 1, None, None, None, None) == T.TBSCI_E_INVAL
+    t = ctypes.c_uint64(77)
+    p = good
+    ptr = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    assert lib.tbsci_submit(None, p.M, p.n_alpha, p.n_beta, ptr(p.h), ptr(p.eri), ptr(p.alpha),
+                            len(p.alpha), ptr(p.beta), len(p.beta), None,
+                            ctypes.byref(t)) == T.TBSCI_E_INVAL
+    assert t.value == 77
+    out = ctypes.c_void_p(5)
+    assert lib.tbsci_server_create(0, 0, 10, ctypes.byref(out)) == T.TBSCI_E_INVAL
+    assert "budget" in T.last_error() and out.value == 5
+    assert lib.tbsci_server_create(0, 1 << 30, -1, ctypes.byref(out)) == T.TBSCI_E_INVAL
+    # batched entry points: n out of range, NULL arrays; n == 0 is a no-op
+    st = (ctypes.c_int * 1)()
+    infos = (T.DavidsonInfo * 1)()
+    assert lib.tbsci_davidson_batch(None, 65, None, infos, st, None) == T.TBSCI_E_INVAL
+    assert lib.tbsci_davidson_batch(None, 1, None, infos, st, None) == T.TBSCI_E_INVAL
+    assert lib.tbsci_davidson_batch(None, 0, None, None, None, None) == T.TBSCI_OK
+    assert lib.tbsci_sigma_batch(None, -1, None, None, 0, None) == T.TBSCI_E_INVAL
+    assert lib.tbsci_sigma_batch(None, 1, None, None, 0, None) == T.TBSCI_E_INVAL

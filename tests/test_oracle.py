@@ -281,3 +281,24 @@ def test_link_table_counts_from_paper():
     strs = np.array([sum(1 << p for p in c) for c in itertools.combinations(range(58), 4)],
                     dtype=np.uint64)
     assert O.count_singles(strs, 58) == cn["entries"]
+
+
+def test_spin_flip_symmetry_and_singlet_sector(oracle_mod):
+    """With identical alpha/beta lists and N_alpha = N_beta, H commutes with
+    F|I J> = (-1)^N |J I> (alpha creators first in the determinant), and a
+    closed-shell determinant |I I> lies in the F = (-1)^N sector, i.e. C = C^T."""
+    O = oracle_mod
+    for (M, N, keep, s1, s2) in ((6, 3, 12, 3, 4), (8, 4, 30, 5, 6), (7, 2, 15, 7, 8)):
+        p = W.make_problem("flip", M, N, keep, s1, s2)
+        sp = O.Space.of(p)
+        H = sp.dense_h()
+        l = len(p.alpha)
+        F = np.zeros((l * l, l * l))
+        for i in range(l):
+            for j in range(l):
+                F[j * l + i, i * l + j] = (-1) ** N
+        assert np.abs(H @ F - F @ H).max() <= 1e-13 * np.abs(H).max()
+        # the symmetric-C subspace is F-invariant with eigenvalue (-1)^N
+        C = np.random.default_rng(1).normal(size=(l, l))
+        C = C + C.T
+        assert np.allclose(F @ C.ravel(), (-1) ** N * C.ravel())

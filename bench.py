@@ -159,6 +159,11 @@ def parse():
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic for scaling profiler byte counters)")
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 sigma leg")
+    ap.add_argument("--serving-requests", type=int, default=48,
+                    help="requests of the serving mix (0 skips the serving leg; the full "
+                         "mix has 512)")
+    ap.add_argument("--serving-rate", type=float, default=40.0,
+                    help="Poisson arrival rate of the serving mix, requests/s")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarize three rocprofv3 csv runs of this benchmark into "
                          "the profile summary and exit (no GPU)")
@@ -354,8 +359,84 @@ def main():
         print(f"# cpu oracle {n_rows} rows in {tc:.1f}s on {threads} threads, parity {err:.2e}",
               file=sys.stderr, flush=True)
 
-    print(json.dumps(result), flush=True)
     ctx.close()
+    if args.serving_requests > 0:
+        result["serving"] = serving_leg(T, W, args.serving_requests, args.serving_rate)
+    print(json.dumps(result), flush=True)
+
+
+def serving_leg(T, W, n_req, rate):
+    """Serving mix: requests arrive by a Poisson process and are solved to
+    an FP64 residual of 1e-4 in mixed precision by the server (continuous
+    batching); the same requests solved one after another with the FP64
+    single-problem solver give the sequential baseline."""
+    import numpy as np
+    mix = W.serving_mix(n_requests=512, seed=5005, rate_per_s=rate)[:n_req]
+    probs = [W.serving_problem(r) for r in mix]
+    opts = dict(precision=T.TBSCI_MIXED, tol_resid=1e-4, fp32_switch_resid=3e-5, n_max=8,
+                max_iter=600)
+    srv = T.Server(hbm_budget_bytes=64 << 30, batch_ndet_threshold=2_000_000)
+    # warm up the kernels once (first launches load code objects)
+    t = srv.submit(probs[0], **opts)
+    while srv.poll(t) is None:
+        time.sleep(0.001)
+    srv.close()
+    srv = T.Server(hbm_budget_bytes=64 << 30, batch_ndet_threshold=2_000_000)
+    tickets = []
+    t0 = time.perf_counter()
+    for r, p in zip(mix, probs):
+        now = time.perf_counter() - t0
+        if r["t_arrive"] > now:
+            time.sleep(r["t_arrive"] - now)
+        tickets.append(srv.submit(p, **opts))
+    done = {}
+    while len(done) < len(tickets):
+        for tk in tickets:
+            if tk not in done:
+                d = srv.poll(tk)
+                if d is not None:
+                    done[tk] = d
+        time.sleep(0.0005)
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array([done[tk]["latency_s"] for tk in tickets])
+    print(f"# serving {n_req} requests: p50 {np.median(lat):.3f}s p99 "
+          f"{np.percentile(lat, 99):.3f}s makespan {makespan:.2f}s, max batch "
+          f"{st['max_batch']}", file=sys.stderr, flush=True)
+    # sequential FP64 baseline, first come first served
+    t1 = time.perf_counter()
+    seq_e = []
+    for p in probs:
+        c = T.Context.from_problem(p)
+        info, _ = c.davidson(tol_resid=1e-4, n_max=8, max_iter=600, want_vector=False)
+        seq_e.append(info["energy"])
+        c.close()
+    seq_s = time.perf_counter() - t1
+    diff = max(abs(done[tk]["energy"] - e) for tk, e in zip(tickets, seq_e))
+    print(f"# sequential fp64 {seq_s:.2f}s, max |E_serving - E_fp64| {diff:.2e}",
+          file=sys.stderr, flush=True)
+    return {
+        "requests": n_req,
+        "recipe": "M uniform in {10,12,14,16}, N=M/2, 500-4000 strings per spin "
+                  "(log-uniform, clamped), integral seed 50000+i, selection seed 60000+i, "
+                  f"Poisson arrivals {rate}/s (seed 5005); mixed precision to FP64 "
+                  "residual 1e-4; batched when <= 2e6 determinants",
+        "p50_latency_s": float(np.median(lat)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()),
+        "makespan_s": makespan,
+        "throughput_req_per_s": n_req / makespan,
+        "sequential_fp64_s": seq_s,
+        "sequential_fp64_req_per_s": n_req / seq_s,
+        "speedup_vs_sequential_fp64": seq_s / makespan,
+        "max_abs_energy_diff_vs_fp64": diff,
+        "converged": int(sum(1 for tk in tickets if done[tk]["status"] == T.TBSCI_OK)),
+        "batched": int(sum(1 for tk in tickets if done[tk]["batched"])),
+        "max_batch": st["max_batch"],
+        "ticks": st["ticks"],
+        "hbm_reserved_peak": st["hbm_reserved_peak"],
+    }
 
 
 if __name__ == "__main__":

@@ -117,7 +117,7 @@ int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int pr
 int tbsci_diag(tbsci_ctx *ctx, double *diag_dev, void *stream);
 
 typedef struct {
-    int n_max;                /* subspace size that triggers a collapse restart, 2..64 */
+    int n_max;                /* subspace size that triggers a restart, 2..16          */
     int max_iter;             /* cap on sigma builds (both phases together)            */
     int precision;            /* TBSCI_FP64 or TBSCI_MIXED                              */
     double tol_resid;         /* stop when the FP64 residual norm <= tol_resid          */
@@ -165,11 +165,15 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
  *             vector (unit norm, largest-magnitude entry positive)
  *   info      host, required
  * Returns TBSCI_OK, or TBSCI_E_NOTCONV with info filled when the tolerance
- * was not met.  Synchronous with respect to the host.  Allocates its
- * workspace ((2 n_max + 5) FP64 vectors, plus two FP32 vectors for MIXED):
- * the basis V and its images H V, the Ritz vector, its image, the
- * correction, and the previous Ritz direction with its image, which the
- * restart keeps next to the Ritz vector.
+ * was not met (TBSCI_E_INVAL for a zero guess).  Synchronous with respect
+ * to the host, with one host synchronisation per iteration (the correction
+ * and its sigma are built before the host sees that iteration's residual,
+ * so a converged solve has built one sigma more than it used; info.iters
+ * counts it).  Allocates its workspace ((2 n_max + 6) FP64 vectors, plus
+ * two FP32 vectors for MIXED): the basis V and its images H V, the Ritz
+ * vector and its image, the correction and its image, and the previous
+ * Ritz direction with its image, which the restart keeps next to the Ritz
+ * vector.
  */
 int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double *guess_dev,
                    double *C_out_dev, tbsci_davidson_info *info, void *stream);
@@ -196,7 +200,7 @@ int tbsci_sigma_batch(tbsci_ctx *const *ctxs, int n, const void *const *C_dev,
  * tbsci_davidson_batch: the lowest eigenvalue of every problem, solved in
  * lock step (one Davidson iteration of every unfinished problem per round,
  * one host synchronisation per round).  opts: NULL for defaults, else an
- * array of n (n_max at most 16).  infos[i] and status[i] (TBSCI_OK or
+ * array of n.  infos[i] and status[i] (TBSCI_OK or
  * TBSCI_E_NOTCONV) receive problem i's result.  The start vector is that
  * of tbsci_davidson without a guess.  Eigenvectors are not
  * returned.  Each problem holds (2 n_max + 6) FP64 vectors, plus two FP32

@@ -1,9 +1,9 @@
-// Lock-step batched Davidson (grouped vector kernels, the engine, and the
-// C entry points tbsci_sigma_batch / tbsci_davidson_batch).  The iteration
-// is the single-problem solver's (paper Sec. II.B Davidson on the sigma
-// product, Sec. III.C bounded restart, Sec. III.A single-precision sigma
-// with double precision elsewhere); what differs is only how the work of
-// many problems is issued.
+// Davidson solver engine (grouped vector kernels, the round scheduler) and
+// the C entry points tbsci_davidson, tbsci_davidson_batch and
+// tbsci_sigma_batch.  The iteration is Davidson on the sigma product (paper
+// Sec. II.B), with a bounded restart (Sec. III.C: the stored vectors stay
+// bounded by the subspace size) and, in mixed precision, a single-precision
+// sigma with everything else in double precision (Sec. III.A).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -20,26 +20,29 @@ namespace {
 
 constexpr int kB = 256;
 constexpr int kSV = kBatchMaxVec;
-constexpr int kNbMax = 256;
+constexpr int kNbMax = 2048;
 // scalar area of a slot (doubles)
 constexpr int sCol = 0;         // [kSV] V_i . W_new
-constexpr int sR2 = kSV;        // |r|^2 of the tick's Ritz pair
-constexpr int sTn0 = kSV + 1;   // |t|^2 before Gram-Schmidt
-constexpr int sTn2 = kSV + 2;   // |t|^2 after Gram-Schmidt (t normalised first)
+constexpr int sR2 = kSV;        // |r|^2 of the round's Ritz pair
+constexpr int sTn2 = kSV + 2;   // |t|^2 after Gram-Schmidt
 constexpr int sN2 = kSV + 3;    // |previous direction|^2 after re-orthogonalisation
 constexpr int sG = kSV + 4;     // x.Wx, x.Wxp, xp.Wx, xp.Wxp
 constexpr int sArg = kSV + 8;   // start index
-constexpr int sCoef = 2 * kSV;  // [kSV] projection coefficients
+constexpr int sGN = kSV + 9;    // |guess|^2
+constexpr int sSign = kSV + 10; // sign of the output vector
+constexpr int sRO = kSV + 11;   // re-orthogonalisation coefficient
+constexpr int sD1 = 2 * kSV;    // [kSV] first-pass coefficients, then |t|^2
+constexpr int sD2 = 3 * kSV;    // [kSV] second-pass coefficients
 constexpr int kScal = 4 * kSV;  // row length
-static_assert(sCoef + kSV <= kScal, "scalar area");
 
 // One slot's part of a grouped launch.  Grid-stride kernels give slot d the
-// blocks [blk0, blk0 + nb); the reduce and start kernels index d directly.
+// blocks [blk0, blk0 + nb); the reduce and per-slot kernels index d directly.
 struct VDesc {
     int64_t blk0, n;
     int32_t nb, k;
-    int32_t dst, src;  // scalar-area indices (reduce target; coefficient / norm source)
-    double thresh;     // scale: norms at or below it scale by 0
+    int32_t dst, src, src2;  // scalar-area indices
+    int32_t flip;
+    double thresh;
     double *o0, *o1, *o2;
     const double *in;
     float *f;
@@ -49,7 +52,7 @@ struct VDesc {
     double c[kSV];
     double theta, floor_;
     int64_t lb;
-    int32_t M, flip;
+    int32_t M, pad;
     const uint64_t *astr;
     const double *da, *db, *jb;
 };
@@ -68,22 +71,36 @@ __device__ __forceinline__ const VDesc &slot_of(const VDesc *__restrict__ d, int
     return d[lo];
 }
 
-__device__ __forceinline__ double block_sum(double s, double *red) {
-    red[threadIdx.x] = s;
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// out[i * kNbMax] = block sum of acc[i], i < k (fixed order: deterministic)
+__device__ __forceinline__ void block_sums(const double (&acc)[kSV], int k, double *out) {
+    __shared__ double red[kB / 64][kSV];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < kSV; ++i)
+        if (i < k) {
+            const double s = wave_sum(acc[i]);
+            if (l == 0) red[w][i] = s;
+        }
     __syncthreads();
-    for (int off = kB / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
+    if ((int)threadIdx.x < k) {
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < kB / 64; ++ww) s += red[ww][threadIdx.x];
+        out[threadIdx.x * kNbMax] = s;
     }
-    const double r = red[0];
     __syncthreads();
-    return r;
 }
 
 #define TB_SLOT_LOOP(e, lblk, t) \
     for (int64_t t = lblk * kB + threadIdx.x; t < e.n; t += (int64_t)e.nb * kB)
 
-// H_KK from the per-string parts (as in the single solver)
+// H_KK from the per-string parts
 __device__ __forceinline__ double diag_at(const VDesc &e, int64_t t) {
     const int64_t ia = t / e.lb, ib = t - ia * e.lb;
     double d = e.da[ia] + e.db[ib];
@@ -92,18 +109,50 @@ __device__ __forceinline__ double diag_at(const VDesc &e, int64_t t) {
     return d;
 }
 
+// (value, index) pair reduction over the block: smallest (MIN) or largest
+// value, first index on ties; every thread receives the result
+template <bool MIN>
+__device__ __forceinline__ void block_pick(double v, int64_t i, double *pv, int64_t *pi) {
+    __shared__ double sv[kB];
+    __shared__ int64_t si[kB];
+    sv[threadIdx.x] = v;
+    si[threadIdx.x] = i;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            const double v2 = sv[threadIdx.x + off];
+            const int64_t i2 = si[threadIdx.x + off];
+            const double v1 = sv[threadIdx.x];
+            const int64_t i1 = si[threadIdx.x];
+            const bool better = MIN ? v2 < v1 : v2 > v1;
+            if (i2 >= 0 && (i1 < 0 || better || (v2 == v1 && i2 < i1))) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    *pv = sv[0];
+    *pi = si[0];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kB) void gv_fill(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     TB_SLOT_LOOP(e, lb, t) e.o0[t] = 0.0;
+}
+
+__global__ __launch_bounds__(kB) void gv_copy(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    TB_SLOT_LOOP(e, lb, t) e.o0[t] = e.in[t];
 }
 
 // per block: smallest H_KK and its first index
 __global__ __launch_bounds__(kB) void gv_diag_min(const VDesc *__restrict__ d, int nd) {
-    __shared__ double sv[kB];
-    __shared__ int64_t si[kB];
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     double best = 1e308;
     int64_t bi = -1;
     TB_SLOT_LOOP(e, lb, t) {
@@ -113,61 +162,35 @@ __global__ __launch_bounds__(kB) void gv_diag_min(const VDesc *__restrict__ d, i
             bi = t;
         }
     }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int off = kB / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            const double v2 = sv[threadIdx.x + off];
-            const int64_t i2 = si[threadIdx.x + off];
-            if (i2 >= 0 && (v2 < sv[threadIdx.x] ||
-                            (v2 == sv[threadIdx.x] && (si[threadIdx.x] < 0 || i2 < si[threadIdx.x])))) {
-                sv[threadIdx.x] = v2;
-                si[threadIdx.x] = i2;
-            }
-        }
-        __syncthreads();
-    }
+    double pv;
+    int64_t pi;
+    block_pick<true>(best, bi, &pv, &pi);
     if (threadIdx.x == 0) {
-        e.partial[lb] = sv[0];
-        e.partial[kNbMax + lb] = (double)si[0];
+        e.partial[lb] = pv;
+        e.partial[kNbMax + lb] = (double)pi;
     }
 }
 
 // one block per slot: the start vector is the unit vector on the smallest
-// H_KK (first on ties)
+// H_KK (first on ties); in a flip-symmetric space an open-shell |I J> is
+// paired with |J I>
 __global__ __launch_bounds__(kB) void gv_argmin_unit(const VDesc *__restrict__ d) {
-    const VDesc &e = d[blockIdx.x];
-    __shared__ double sv[kB];
-    __shared__ int64_t si[kB];
+    const VDesc e = d[blockIdx.x];
     double best = 1e308;
     int64_t bi = -1;
     for (int b = threadIdx.x; b < e.nb; b += kB) {
         const double v = e.partial[b];
         const int64_t i = (int64_t)e.partial[kNbMax + b];
-        if (i >= 0 && (v < best || (v == best && (bi < 0 || i < bi)))) {
+        if (i >= 0 && (bi < 0 || v < best || (v == best && i < bi))) {
             best = v;
             bi = i;
         }
     }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int off = kB / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            const double v2 = sv[threadIdx.x + off];
-            const int64_t i2 = si[threadIdx.x + off];
-            if (i2 >= 0 && (v2 < sv[threadIdx.x] ||
-                            (v2 == sv[threadIdx.x] && (si[threadIdx.x] < 0 || i2 < si[threadIdx.x])))) {
-                sv[threadIdx.x] = v2;
-                si[threadIdx.x] = i2;
-            }
-        }
-        __syncthreads();
-    }
+    double pv;
+    int64_t pi;
+    block_pick<true>(best, bi, &pv, &pi);
     if (threadIdx.x == 0) {
-        // in a flip-symmetric space an open-shell |I J> is paired with |J I>
-        const int64_t at = si[0] >= 0 ? si[0] : 0;
+        const int64_t at = pi >= 0 ? pi : 0;
         const int64_t ia = at / e.lb, ib = at - ia * e.lb;
         const int64_t at2 = e.flip ? ib * e.lb + ia : at;
         const double val = at2 == at ? 1.0 : 0.70710678118654752440;
@@ -177,96 +200,203 @@ __global__ __launch_bounds__(kB) void gv_argmin_unit(const VDesc *__restrict__ d
     }
 }
 
+// per block: largest |x| and its first index
+__global__ __launch_bounds__(kB) void gv_absmax(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    double best = -1.0;
+    int64_t bi = -1;
+    TB_SLOT_LOOP(e, lb, t) {
+        const double v = fabs(e.in[t]);
+        if (v > best) {
+            best = v;
+            bi = t;
+        }
+    }
+    double pv;
+    int64_t pi;
+    block_pick<false>(best, bi, &pv, &pi);
+    if (threadIdx.x == 0) {
+        e.partial[lb] = pv;
+        e.partial[kNbMax + lb] = (double)pi;
+    }
+}
+
+// one block per slot: the sign that makes the largest-magnitude entry
+// positive
+__global__ __launch_bounds__(kB) void gv_absmax_sign(const VDesc *__restrict__ d) {
+    const VDesc e = d[blockIdx.x];
+    double best = -1.0;
+    int64_t bi = -1;
+    for (int b = threadIdx.x; b < e.nb; b += kB) {
+        const double v = e.partial[b];
+        const int64_t i = (int64_t)e.partial[kNbMax + b];
+        if (i >= 0 && (bi < 0 || v > best || (v == best && i < bi))) {
+            best = v;
+            bi = i;
+        }
+    }
+    double pv;
+    int64_t pi;
+    block_pick<false>(best, bi, &pv, &pi);
+    if (threadIdx.x == 0) e.scal[e.dst] = (pi >= 0 && e.in[pi] < 0.0) ? -1.0 : 1.0;
+}
+
+__global__ __launch_bounds__(kB) void gv_signed_copy(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    const double s = e.scal[e.src];
+    TB_SLOT_LOOP(e, lb, t) e.o0[t] = s * e.in[t];
+}
+
 // x = V y, wx = W y, t = (wx - theta x) / (theta - H_KK) with a floor;
 // partial sums of |wx - theta x|^2
 __global__ __launch_bounds__(kB) void gv_ritz(const VDesc *__restrict__ d, int nd) {
-    __shared__ double red[kB];
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
-    double s = 0.0;
+    const VDesc e = slot_of(d, nd, lb);
+    double acc[kSV] = {};
     TB_SLOT_LOOP(e, lb, t) {
         double xv = 0.0, wv = 0.0;
-        for (int i = 0; i < e.k; ++i) {
-            xv += e.c[i] * e.a[i][t];
-            wv += e.c[i] * e.b[i][t];
-        }
+#pragma unroll
+        for (int i = 0; i < kSV; ++i)
+            if (i < e.k) {
+                xv += e.c[i] * e.a[i][t];
+                wv += e.c[i] * e.b[i][t];
+            }
         const double r = wv - e.theta * xv;
-        s += r * r;
+        acc[0] += r * r;
         double den = e.theta - diag_at(e, t);
         if (fabs(den) < e.floor_) den = den < 0.0 ? -e.floor_ : e.floor_;
         e.o0[t] = xv;
         e.o1[t] = wv;
         e.o2[t] = r / den;
     }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) e.partial[lb] = s;
+    block_sums(acc, 1, e.partial + lb);
 }
 
 // o0 = sum_i c_i a_i, o1 = sum_i c_i b_i
 __global__ __launch_bounds__(kB) void gv_lincomb2(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     TB_SLOT_LOOP(e, lb, t) {
         double xv = 0.0, wv = 0.0;
-        for (int i = 0; i < e.k; ++i) {
-            xv += e.c[i] * e.a[i][t];
-            wv += e.c[i] * e.b[i][t];
-        }
+#pragma unroll
+        for (int i = 0; i < kSV; ++i)
+            if (i < e.k) {
+                xv += e.c[i] * e.a[i][t];
+                wv += e.c[i] * e.b[i][t];
+            }
         e.o0[t] = xv;
         e.o1[t] = wv;
     }
 }
 
-// partial[i][blk] = block's part of a_i . in, i < k
+// partial[i][blk] = block's part of a_i . in, i < k, with `in` read once
 __global__ __launch_bounds__(kB) void gv_dots(const VDesc *__restrict__ d, int nd) {
-    __shared__ double red[kB];
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
-    for (int i = 0; i < e.k; ++i) {
-        const double *__restrict__ ai = e.a[i];
-        double s = 0.0;
-        TB_SLOT_LOOP(e, lb, t) s += ai[t] * e.in[t];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) e.partial[i * kNbMax + lb] = s;
+    const VDesc e = slot_of(d, nd, lb);
+    double acc[kSV] = {};
+    TB_SLOT_LOOP(e, lb, t) {
+        const double x = e.in[t];
+#pragma unroll
+        for (int i = 0; i < kSV; ++i)
+            if (i < e.k) acc[i] += e.a[i][t] * x;
     }
+    block_sums(acc, e.k, e.partial + lb);
+}
+
+// o0 -= sum_i scal[src + i] a_i, then partial[i][blk] = a_i . o0: the
+// subtraction of the first Gram-Schmidt pass with the dot products of the
+// second
+__global__ __launch_bounds__(kB) void gv_subdots(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    double cf[kSV], acc[kSV] = {};
+#pragma unroll
+    for (int i = 0; i < kSV; ++i) cf[i] = i < e.k ? e.scal[e.src + i] : 0.0;
+    TB_SLOT_LOOP(e, lb, t) {
+        double av[kSV];
+        double v = e.o0[t];
+#pragma unroll
+        for (int i = 0; i < kSV; ++i)
+            if (i < e.k) {
+                av[i] = e.a[i][t];
+                v -= cf[i] * av[i];
+            }
+        e.o0[t] = v;
+#pragma unroll
+        for (int i = 0; i < kSV; ++i)
+            if (i < e.k) acc[i] += av[i] * v;
+    }
+    block_sums(acc, e.k, e.partial + lb);
+}
+
+// o0 -= sum_i scal[src + i] a_i, then partial[0][blk] = |o0|^2
+__global__ __launch_bounds__(kB) void gv_subnorm(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    double cf[kSV], acc[kSV] = {};
+#pragma unroll
+    for (int i = 0; i < kSV; ++i) cf[i] = i < e.k ? e.scal[e.src + i] : 0.0;
+    TB_SLOT_LOOP(e, lb, t) {
+        double v = e.o0[t];
+#pragma unroll
+        for (int i = 0; i < kSV; ++i)
+            if (i < e.k) v -= cf[i] * e.a[i][t];
+        e.o0[t] = v;
+        acc[0] += v * v;
+    }
+    block_sums(acc, 1, e.partial + lb);
 }
 
 // scal[dst + i] = sum over the slot's blocks of partial[i][.]; block = (slot, i)
 __global__ __launch_bounds__(kB) void gv_reduce(const VDesc *__restrict__ d, int kmax) {
     __shared__ double red[kB];
-    const VDesc &e = d[blockIdx.x / kmax];
+    const VDesc e = d[blockIdx.x / kmax];
     const int i = blockIdx.x % kmax;
     if (i >= e.k) return;
     double s = 0.0;
     for (int b = threadIdx.x; b < e.nb; b += kB) s += e.partial[i * kNbMax + b];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) e.scal[e.dst + i] = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e.scal[e.dst + i] = red[0];
 }
 
 // o0 -= sum_i scal[src + i] a_i (and o1 -= sum_i scal[src + i] b_i)
 __global__ __launch_bounds__(kB) void gv_subproj(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     double cf[kSV];
-    for (int i = 0; i < e.k; ++i) cf[i] = e.scal[e.src + i];
+#pragma unroll
+    for (int i = 0; i < kSV; ++i) cf[i] = i < e.k ? e.scal[e.src + i] : 0.0;
     TB_SLOT_LOOP(e, lb, t) {
         double v = e.o0[t];
-        for (int i = 0; i < e.k; ++i) v -= cf[i] * e.a[i][t];
+#pragma unroll
+        for (int i = 0; i < kSV; ++i)
+            if (i < e.k) v -= cf[i] * e.a[i][t];
         e.o0[t] = v;
         if (e.o1) {
             double w = e.o1[t];
-            for (int i = 0; i < e.k; ++i) w -= cf[i] * e.b[i][t];
+#pragma unroll
+            for (int i = 0; i < kSV; ++i)
+                if (i < e.k) w -= cf[i] * e.b[i][t];
             e.o1[t] = w;
         }
     }
 }
 
-// o0 (and o1) *= 1 / sqrt(scal[src]), or 0 when that norm is <= thresh
+// o0 (and o1) *= 1 / |.| with |.| = sqrt(scal[src]), or by 0 when |.| <=
+// thresh (times sqrt(scal[src2]) when src2 >= 0: a relative test)
 __global__ __launch_bounds__(kB) void gv_scale(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     const double nrm = sqrt(fmax(e.scal[e.src], 0.0));
-    const double f = nrm > e.thresh ? 1.0 / nrm : 0.0;
+    const double ref = e.src2 >= 0 ? sqrt(fmax(e.scal[e.src2], 0.0)) : 1.0;
+    const double f = nrm > e.thresh * ref ? 1.0 / nrm : 0.0;
     TB_SLOT_LOOP(e, lb, t) {
         e.o0[t] *= f;
         if (e.o1) e.o1[t] *= f;
@@ -277,67 +407,72 @@ __global__ __launch_bounds__(kB) void gv_scale(const VDesc *__restrict__ d, int 
 // the slot's tile-pair block count here
 __global__ __launch_bounds__(kB) void gv_flip_sym(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     flip_sym_block(lb, e.lb, e.o0);
 }
 
 __global__ __launch_bounds__(kB) void gv_to_f32(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     TB_SLOT_LOOP(e, lb, t) e.f[t] = (float)e.in[t];
 }
 
 __global__ __launch_bounds__(kB) void gv_to_f64(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
-    const VDesc &e = slot_of(d, nd, lb);
+    const VDesc e = slot_of(d, nd, lb);
     TB_SLOT_LOOP(e, lb, t) e.o0[t] = (double)e.f[t];
 }
 
 #undef TB_SLOT_LOOP
 
-// operations of a tick, in issue order
+// operations of a round, in issue order (a slot uses a subsequence)
 enum Op {
-    O_FILL, O_DMIN, O_AMIN,
-    O_RITZ, O_RITZ_R, O_SYM,
-    O_LC,
-    O_RO1_D, O_RO1_R, O_RO1_S, O_RO2_D, O_RO2_R, O_RO2_S,
-    O_N2_D, O_N2_R, O_N2_S,
-    O_G0_D, O_G0_R, O_G1_D, O_G1_R,
-    O_T0_D, O_T0_R, O_T0_S,
-    O_GS1_D, O_GS1_R, O_GS1_S, O_GS2_D, O_GS2_R, O_GS2_S,
-    O_TN_D, O_TN_R, O_TN_S,
+    O_AMAX, O_AMAX_S, O_OUT,                        // finish: signed copy to the output
+    O_FILL, O_DMIN, O_AMIN,                         // start on the smallest H_KK
+    O_GCOPY, O_GN_D, O_GN_R, O_GN_S,                // start from a guess
+    O_RITZ, O_RITZ_R, O_SYM,                        // Ritz pair, residual, correction
+    O_LC, O_RO1_D, O_RO1_R, O_RO1_S, O_RO2_D, O_RO2_R, O_RO2_S,  // restart
+    O_N2_D, O_N2_R, O_N2_S, O_G0_D, O_G0_R, O_G1_D, O_G1_R,
+    O_D1, O_D1_R, O_S1D2, O_S1D2_R, O_S2N, O_S2N_R, O_TSCALE,    // Gram-Schmidt
     O_CVT32,
     O_SIGMA,  // marker: grouped sigma builds
     O_CVT64,
-    O_COL_D, O_COL_R,
+    O_COL_D, O_COL_R,                               // new column of V^T H V
     O_N
 };
 
 enum Kind {
-    K_FILL, K_DMIN, K_AMIN, K_RITZ, K_RED, K_SYM, K_LC, K_DOT, K_SUB, K_SCALE, K_F32, K_F64, K_NONE
+    K_FILL, K_COPY, K_DMIN, K_AMIN, K_AMAX, K_ASIGN, K_SCOPY, K_RITZ, K_RED, K_SYM, K_LC,
+    K_DOT, K_SUB, K_SUBDOT, K_SUBNORM, K_SCALE, K_F32, K_F64, K_NONE
 };
 
 Kind kind_of(int op) {
     switch (op) {
+        case O_AMAX: return K_AMAX;
+        case O_AMAX_S: return K_ASIGN;
+        case O_OUT: return K_SCOPY;
         case O_FILL: return K_FILL;
         case O_DMIN: return K_DMIN;
         case O_AMIN: return K_AMIN;
+        case O_GCOPY: return K_COPY;
         case O_RITZ: return K_RITZ;
         case O_SYM: return K_SYM;
         case O_LC: return K_LC;
-        case O_RO1_S: case O_RO2_S: case O_GS1_S: case O_GS2_S: return K_SUB;
-        case O_N2_S: case O_T0_S: case O_TN_S: return K_SCALE;
+        case O_RO1_S: case O_RO2_S: return K_SUB;
+        case O_S1D2: return K_SUBDOT;
+        case O_S2N: return K_SUBNORM;
+        case O_GN_S: case O_N2_S: case O_TSCALE: return K_SCALE;
         case O_CVT32: return K_F32;
         case O_CVT64: return K_F64;
         case O_SIGMA: return K_NONE;
-        case O_RITZ_R: case O_RO1_R: case O_RO2_R: case O_N2_R: case O_G0_R: case O_G1_R:
-        case O_T0_R: case O_GS1_R: case O_GS2_R: case O_TN_R: case O_COL_R: return K_RED;
+        case O_GN_R: case O_RITZ_R: case O_RO1_R: case O_RO2_R: case O_N2_R: case O_G0_R:
+        case O_G1_R: case O_D1_R: case O_S1D2_R: case O_S2N_R: case O_COL_R: return K_RED;
         default: return K_DOT;
     }
 }
 
 int blocks_for_slot(int64_t n) {
-    return (int)std::min<int64_t>(kNbMax, std::max<int64_t>(1, (n + 4 * kB - 1) / (4 * kB)));
+    return (int)std::min<int64_t>(kNbMax, std::max<int64_t>(1, (n + 16 * kB - 1) / (16 * kB)));
 }
 
 size_t page(size_t bytes) { return (std::max<size_t>(bytes, 8) + 4095) & ~size_t(4095); }
@@ -381,6 +516,7 @@ BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o) {
         s->o = o;
         s->n = c->sp[0].l * c->sp[1].l;
         s->nb = blocks_for_slot(s->n);
+        s->sym = c->flip;
         auto get = [&](size_t bytes) {
             void *p = nullptr;
             TB_HIP(hipMalloc(&p, bytes));
@@ -418,6 +554,7 @@ void BatchEngine::add(BatchSlot *s) {
     free_rows_.pop_back();
     s->phase = BatchSlot::kStart;
     s->fp32 = s->o.precision == TBSCI_MIXED;
+    if (s->guess) s->sym = false;  // a caller's start vector picks its own sector
     s->t0 = std::chrono::steady_clock::now();
     memset(&s->info, 0, sizeof(s->info));
     act_.push_back(s);
@@ -449,6 +586,7 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         d.nb = s.nb;
         d.partial = s.partial;
         d.scal = scal;
+        d.src2 = -1;
         return d;
     };
     auto dots = [&](int op, const std::vector<double *> &a, const double *in, int dst) {
@@ -462,24 +600,18 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         r.dst = dst;
         S.ops[op + 1].push_back(r);
     };
-    auto subproj = [&](int op, double *o0, const std::vector<double *> &a, double *o1,
-                       const std::vector<double *> &b) {
-        VDesc d = base();
-        d.k = (int)a.size();
-        for (int i = 0; i < d.k; ++i) {
-            d.a[i] = a[i];
-            d.b[i] = o1 ? b[i] : nullptr;
-        }
-        d.o0 = o0;
-        d.o1 = o1;
-        d.src = sCoef;
-        S.ops[op].push_back(d);
+    auto reduce = [&](int op, int k, int dst) {
+        VDesc r = base();
+        r.k = k;
+        r.dst = dst;
+        S.ops[op].push_back(r);
     };
-    auto scale = [&](int op, double *o0, double *o1, int src, double thresh) {
+    auto scale = [&](int op, double *o0, double *o1, int src, int src2, double thresh) {
         VDesc d = base();
         d.o0 = o0;
         d.o1 = o1;
         d.src = src;
+        d.src2 = src2;
         d.thresh = thresh;
         S.ops[op].push_back(d);
     };
@@ -497,11 +629,27 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         pool.pop_back();
         return p;
     };
+
+    if (s.phase == BatchSlot::kFinish) {  // signed copy of the Ritz vector
+        VDesc m = base();
+        m.in = s.X;
+        S.ops[O_AMAX].push_back(m);
+        VDesc g = base();
+        g.in = s.X;
+        g.dst = sSign;
+        S.ops[O_AMAX_S].push_back(g);
+        VDesc o = base();
+        o.in = s.X;
+        o.o0 = s.out;
+        o.src = sSign;
+        S.ops[O_OUT].push_back(o);
+        return;
+    }
+
     const double *sig_in = nullptr;
     double *sig_out = nullptr;
-
     if (s.phase == BatchSlot::kStart || s.phase == BatchSlot::kHandover) {
-        if (s.phase == BatchSlot::kStart) {
+        if (s.phase == BatchSlot::kStart && !s.guess) {
             P.V0 = take(s.vfree);
             VDesc f = base();
             f.o0 = P.V0;
@@ -513,8 +661,16 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
             u.o0 = P.V0;
             u.dst = sArg;
             u.lb = s.c->sp[1].l;
-            u.flip = s.c->flip ? 1 : 0;
+            u.flip = s.sym ? 1 : 0;
             S.ops[O_AMIN].push_back(u);
+        } else if (s.phase == BatchSlot::kStart) {
+            P.V0 = take(s.vfree);
+            VDesc cp = base();
+            cp.o0 = P.V0;
+            cp.in = s.guess;
+            S.ops[O_GCOPY].push_back(cp);
+            dots(O_GN_D, {P.V0}, P.V0, sGN);
+            scale(O_GN_S, P.V0, nullptr, sGN, -1, 0.0);
         } else {
             P.V0 = s.X;  // the Ritz vector of the FP32 phase
             s.X = nullptr;
@@ -561,11 +717,8 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         r.o1 = P.WXn;
         r.o2 = P.T;
         S.ops[O_RITZ].push_back(r);
-        VDesc rr = base();
-        rr.k = 1;
-        rr.dst = sR2;
-        S.ops[O_RITZ_R].push_back(rr);
-        if (s.c->flip) {  // keep the solve in the C = C^T sector
+        reduce(O_RITZ_R, 1, sR2);
+        if (s.sym) {  // keep the solve in the C = C^T sector
             VDesc y = base();
             const int64_t l = s.c->sp[1].l, nt = (l + 31) / 32;
             y.nb = (int32_t)(nt * nt);
@@ -603,12 +756,20 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
                 // V z is a difference of nearly equal vectors near
                 // convergence: re-orthogonalise against x twice, with the
                 // same combination on its image
-                dots(O_RO1_D, {P.Xn}, P.XP, sCoef);
-                subproj(O_RO1_S, P.XP, {P.Xn}, P.WXP, {P.WXn});
-                dots(O_RO2_D, {P.Xn}, P.XP, sCoef);
-                subproj(O_RO2_S, P.XP, {P.Xn}, P.WXP, {P.WXn});
+                for (int pass = 0; pass < 2; ++pass) {
+                    const int op = pass == 0 ? O_RO1_D : O_RO2_D;
+                    dots(op, {P.Xn}, P.XP, sRO);
+                    VDesc sp = base();
+                    sp.k = 1;
+                    sp.a[0] = P.Xn;
+                    sp.b[0] = P.WXn;
+                    sp.o0 = P.XP;
+                    sp.o1 = P.WXP;
+                    sp.src = sRO;
+                    S.ops[op + 2].push_back(sp);
+                }
                 dots(O_N2_D, {P.XP}, P.XP, sN2);
-                scale(O_N2_S, P.XP, P.WXP, sN2, 1e-8);
+                scale(O_N2_S, P.XP, P.WXP, sN2, -1, 1e-8);
                 dots(O_G0_D, {P.WXn, P.WXP}, P.Xn, sG);
                 dots(O_G1_D, {P.WXn, P.WXP}, P.XP, sG + 2);
                 P.Vb = {P.Xn, P.XP};
@@ -622,21 +783,27 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
             P.Vb = s.V;
             P.Wb = s.W;
         }
-        // normalise t (the drop test is relative), two Gram-Schmidt passes
-        // against the basis it joins, normalise again
-        dots(O_T0_D, {P.T}, P.T, sTn0);
-        scale(O_T0_S, P.T, nullptr, sTn0, 0.0);
-        dots(O_GS1_D, P.Vb, P.T, sCoef);
-        subproj(O_GS1_S, P.T, P.Vb, nullptr, {});
-        dots(O_GS2_D, P.Vb, P.T, sCoef);
-        subproj(O_GS2_S, P.T, P.Vb, nullptr, {});
-        dots(O_TN_D, {P.T}, P.T, sTn2);
-        scale(O_TN_S, P.T, nullptr, sTn2, 1e-10);
+        // two Gram-Schmidt passes against the basis t joins, then t is
+        // normalised; a t left with at most 1e-10 of its norm is dropped
+        const int kb = (int)P.Vb.size();
+        std::vector<double *> with_t = P.Vb;
+        with_t.push_back(P.T);
+        dots(O_D1, with_t, P.T, sD1);  // coefficients, and |t|^2 at sD1 + kb
+        VDesc sd = base();
+        sd.k = kb;
+        for (int i = 0; i < kb; ++i) sd.a[i] = P.Vb[i];
+        sd.o0 = P.T;
+        sd.src = sD1;
+        S.ops[O_S1D2].push_back(sd);
+        reduce(O_S1D2_R, kb, sD2);
+        VDesc sn = sd;
+        sn.src = sD2;
+        S.ops[O_S2N].push_back(sn);
+        reduce(O_S2N_R, 1, sTn2);
+        scale(O_TSCALE, P.T, nullptr, sTn2, sD1 + kb, 1e-10);
         sig_in = P.T;
         sig_out = P.TW;
-        std::vector<double *> all = P.Vb;
-        all.push_back(P.T);
-        dots(O_COL_D, all, P.TW, sCol);
+        dots(O_COL_D, with_t, P.TW, sCol);
     }
     if (P.sig32) {
         VDesc a = base();
@@ -665,7 +832,7 @@ bool BatchEngine::tick() {
     for (BatchSlot *s : act_) plan(*s, S);
     max_group = std::max(max_group, (int)act_.size());
 
-    // stage every table of the tick, one transfer
+    // stage every table of the round, one transfer
     const VDesc *dev[O_N] = {};
     int64_t blocks[O_N] = {};
     int kmax[O_N] = {};
@@ -676,7 +843,7 @@ bool BatchEngine::tick() {
         if (kd == K_RED) {
             for (auto &d : v) kmax[op] = std::max(kmax[op], (int)d.k);
             blocks[op] = (int64_t)v.size() * kmax[op];
-        } else if (kd == K_AMIN) {
+        } else if (kd == K_AMIN || kd == K_ASIGN) {
             blocks[op] = (int64_t)v.size();
         } else {
             int64_t b = 0;
@@ -694,24 +861,32 @@ bool BatchEngine::tick() {
         if (S.ops[op].empty()) return;
         const unsigned g = (unsigned)blocks[op];
         const int nd = (int)S.ops[op].size();
+        const VDesc *d = dev[op];
         switch (kind_of(op)) {
-            case K_FILL: gv_fill<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_DMIN: gv_diag_min<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_AMIN: gv_argmin_unit<<<g, kB, 0, st_>>>(dev[op]); break;
-            case K_RITZ: gv_ritz<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_RED: gv_reduce<<<g, kB, 0, st_>>>(dev[op], kmax[op]); break;
-            case K_SYM: gv_flip_sym<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_LC: gv_lincomb2<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_DOT: gv_dots<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_SUB: gv_subproj<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_SCALE: gv_scale<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_F32: gv_to_f32<<<g, kB, 0, st_>>>(dev[op], nd); break;
-            case K_F64: gv_to_f64<<<g, kB, 0, st_>>>(dev[op], nd); break;
+            case K_FILL: gv_fill<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_COPY: gv_copy<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_DMIN: gv_diag_min<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_AMIN: gv_argmin_unit<<<g, kB, 0, st_>>>(d); break;
+            case K_AMAX: gv_absmax<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_ASIGN: gv_absmax_sign<<<g, kB, 0, st_>>>(d); break;
+            case K_SCOPY: gv_signed_copy<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_RITZ: gv_ritz<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_RED: gv_reduce<<<g, kB, 0, st_>>>(d, kmax[op]); break;
+            case K_SYM: gv_flip_sym<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_LC: gv_lincomb2<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_DOT: gv_dots<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_SUB: gv_subproj<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_SUBDOT: gv_subdots<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_SUBNORM: gv_subnorm<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_SCALE: gv_scale<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_F32: gv_to_f32<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_F64: gv_to_f64<<<g, kB, 0, st_>>>(d, nd); break;
             case K_NONE: break;
         }
         TB_HIP(hipGetLastError());
     };
     for (int op = 0; op < O_SIGMA; ++op) launch(op);
+    const bool sig = !S.c64.empty() || !S.c32.empty();
     TB_HIP(hipEventRecord(ev_[0], st_));
     if (!S.c64.empty())
         launch_sigma_group(S.c64.data(), S.i64.data(), S.o64.data(), (int)S.c64.size(),
@@ -729,7 +904,7 @@ bool BatchEngine::tick() {
                           hipMemcpyDeviceToHost, st_));
     TB_HIP(hipStreamSynchronize(st_));
     float ms = 0.f;
-    TB_HIP(hipEventElapsedTime(&ms, ev_[0], ev_[1]));
+    if (sig) TB_HIP(hipEventElapsedTime(&ms, ev_[0], ev_[1]));
     ++ticks;
 
     std::vector<BatchSlot *> still;
@@ -747,19 +922,32 @@ bool BatchEngine::tick() {
     return true;
 }
 
-void BatchEngine::finish(BatchSlot &s, double *keep) {
-    s.phase = BatchSlot::kDone;
-    if (keep) s.vfree.push_back(keep);
+// The solve has ended with Ritz vector x: one more round writes the output
+// vector when one was asked for, else the slot is done now.
+void BatchEngine::finish(BatchSlot &s, double *x) {
     if (s.fp32) s.info.converged = 0;  // never certified by an FP64 sigma
-    s.status = s.info.converged ? TBSCI_OK : TBSCI_E_NOTCONV;
+    if (s.status == TBSCI_PENDING) s.status = s.info.converged ? TBSCI_OK : TBSCI_E_NOTCONV;
     s.info.energy = s.theta;
     s.info.resid_norm = s.rn;
+    if (s.out && x && s.phase != BatchSlot::kFinish) {
+        s.X = x;
+        s.phase = BatchSlot::kFinish;
+        return;
+    }
+    if (x) s.vfree.push_back(x);
+    s.phase = BatchSlot::kDone;
     s.info.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - s.t0).count();
 }
 
 void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     auto &P = s.p;
     const int nm = s.o.n_max;
+    if (s.phase == BatchSlot::kFinish) {
+        double *x = s.X;
+        s.X = nullptr;
+        finish(s, x);
+        return;
+    }
     s.info.iters++;
     if (P.sig32)
         s.info.iters_fp32++;
@@ -774,6 +962,14 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     };
 
     if (s.phase == BatchSlot::kStart || s.phase == BatchSlot::kHandover) {
+        if (s.phase == BatchSlot::kStart && s.guess && !(r[sGN] > 0.0)) {
+            release_v(P.V0);
+            release_w(P.W0);
+            s.status = TBSCI_E_INVAL;
+            s.msg = "guess vector is zero";
+            finish(s, nullptr);
+            return;
+        }
         if (s.phase == BatchSlot::kHandover) s.fp32 = false;
         s.V = {P.V0};
         s.W = {P.W0};
@@ -787,13 +983,15 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     }
 
     s.rn = std::sqrt(std::max(r[sR2], 0.0));
+    const int kb = (int)P.Vb.size();
+    const double t0n = std::sqrt(std::max(r[sD1 + kb], 0.0));
     const double tn = std::sqrt(std::max(r[sTn2], 0.0));
-    const bool dropped = !(tn >= 1e-10);
+    const bool dropped = !(tn > 1e-10 * t0n);
     if (trace)
-        fprintf(stderr, "tbsci batch: slot %d sigma %d k %d %s theta %.15f resid %.3e\n", s.row,
-                s.info.iters, s.k, s.fp32 ? "fp32" : "fp64", s.theta, s.rn);
+        fprintf(stderr, "tbsci davidson: sigma %d k %d %s theta %.15f resid %.3e\n", s.info.iters,
+                s.k, s.fp32 ? "fp32" : "fp64", s.theta, s.rn);
 
-    // everything of this tick except the Ritz vector goes back to the pools
+    // everything of this round except the Ritz vector goes back to the pools
     auto drop_all_but_x = [&]() {
         for (double *p : s.V) release_v(p);
         for (double *p : s.W) release_w(p);
@@ -807,7 +1005,11 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     };
     bool handover = false;
     if (s.fp32) {
-        // same rule as the single-problem solver
+        // The FP32 phase ends at fp32_switch_resid, or when the residual
+        // has stopped improving close to the FP32 rounding floor of the
+        // sigma build (taken as 2e-6 |theta|), or when no new direction is
+        // left; a plateau well above that floor is slow convergence, which
+        // FP64 would not cure.
         if (s.rn < 0.98 * s.best_rn) {
             s.best_rn = s.rn;
             s.since_best = 0;
@@ -867,13 +1069,50 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
         release_w(P.WXn);
         for (int i = 0; i < s.k; ++i) pos.push_back(i);
     }
-    const int tpos = (int)P.Vb.size();
     s.V.push_back(P.T);
     s.W.push_back(P.TW);
-    pos.push_back(tpos);
+    pos.push_back(kb);
     const int kk = s.k;  // index of the new vector
     for (int i = 0; i <= kk; ++i) s.G[i * nm + kk] = s.G[kk * nm + i] = r[sCol + pos[i]];
     s.k = kk + 1;
+}
+
+int solve_one(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *out,
+              tbsci_davidson_info &info, hipStream_t st, const std::atomic<bool> *abort) {
+    reserve_sigma_workspace(c);
+    BatchSlot *s = BatchEngine::make_slot(&c, o);
+    s->guess = guess;
+    s->out = out;
+    int rc = TBSCI_OK;
+    try {
+        BatchEngine eng(c.device, st);
+        const char *tr = getenv("TBSCI_DAVIDSON_TRACE");  // per-iteration trace on stderr
+        eng.trace = tr && tr[0] && tr[0] != '0';
+        eng.add(s);
+        bool aborted = false;
+        while (eng.tick())
+            if (abort && abort->load()) {
+                aborted = true;
+                break;
+            }
+        info = s->info;
+        if (aborted) {
+            eng.drain();
+            info.energy = s->theta;
+            info.resid_norm = s->rn;
+            info.converged = 0;
+            rc = TBSCI_E_STATE;
+        } else {
+            rc = s->status;
+            if (rc == TBSCI_E_INVAL) throw Error(rc, s->msg);
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        BatchEngine::free_slot(s);
+        throw;
+    }
+    BatchEngine::free_slot(s);
+    return rc;
 }
 
 }  // namespace tbsci
@@ -881,6 +1120,26 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
 using namespace tbsci;
 
 extern "C" {
+
+int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double *guess_dev,
+                   double *C_out_dev, tbsci_davidson_info *info, void *stream) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        Ctx *c = ctx_of(ctx);
+        if (!info) throw Error(TBSCI_E_INVAL, "info is NULL");
+        tbsci_davidson_opts o;
+        tbsci_davidson_default_opts(&o);
+        if (opts) o = *opts;
+        check_opts(o);
+        if (guess_dev) check_dev(guess_dev, c->device, "guess");
+        if (C_out_dev) check_dev(C_out_dev, c->device, "C_out");
+        tbsci_davidson_info tmp;
+        const int rc = solve_one(*c, o, guess_dev, C_out_dev, tmp, (hipStream_t)stream);
+        *info = tmp;
+        if (rc == TBSCI_E_NOTCONV) set_error(rc, "Davidson did not reach the tolerance");
+        return rc;
+    });
+}
 
 int tbsci_sigma_batch(tbsci_ctx *const *ctxs, int n, const void *const *C_dev,
                       void *const *sigma_dev, int precision, void *stream) {
@@ -932,13 +1191,10 @@ int tbsci_davidson_batch(tbsci_ctx *const *ctxs, int n, const tbsci_davidson_opt
             else
                 tbsci_davidson_default_opts(&os[i]);
             check_opts(os[i]);
-            if (os[i].n_max > kBatchMaxVec)
-                throw Error(TBSCI_E_INVAL, "n_max must be at most 16 in a batch");
         }
         TB_HIP(hipSetDevice(cs[0]->device));
         hipStream_t st = (hipStream_t)stream;
         std::vector<BatchSlot *> slots;
-        int rc = TBSCI_OK;
         try {
             BatchEngine eng(cs[0]->device, st);
             const char *tr = getenv("TBSCI_DAVIDSON_TRACE");
@@ -962,7 +1218,7 @@ int tbsci_davidson_batch(tbsci_ctx *const *ctxs, int n, const tbsci_davidson_opt
             throw;
         }
         for (BatchSlot *s : slots) BatchEngine::free_slot(s);
-        return rc;
+        return TBSCI_OK;
     });
 }
 

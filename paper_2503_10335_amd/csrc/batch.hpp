@@ -1,22 +1,27 @@
-// Lock-step batched Davidson over several TPB problems on one device.
+// Davidson solver engine: one or many TPB problems on one device, advanced
+// in lock step.
 //
-// Every active problem ("slot") advances one Davidson iteration per tick.
-// A tick issues each vector operation as ONE grouped launch over all slots
+// Every active problem ("slot") advances one Davidson iteration per round.
+// A round issues each vector operation as ONE grouped launch over all slots
 // that need it, the sigma builds of all slots as one grouped launch per
 // kernel type (per precision), and ends with a single host synchronisation
 // that brings back every slot's k x k scalars.  Slots join and leave
-// between ticks, which is what the serving loop's continuous batching
-// builds on.
+// between rounds, which is what the serving loop's continuous batching
+// builds on; a single solve is a batch of one.
 //
-// The iteration is the one of the single-problem solver (same restart,
-// same mixed-precision hand-over), reorganised so that a tick needs one
-// synchronisation: the correction vector of a tick and its sigma are
-// computed before the host sees the residual of that tick's Ritz pair, so
-// the last tick of a converged slot builds one sigma that is discarded.
-// Reductions use a block count fixed by the slot's size, so the arithmetic
-// of a slot does not depend on which other slots share its launches.
+// One round of a slot: the Ritz pair of the current basis, its residual
+// and preconditioned correction; the restart when the basis is full; two
+// Gram-Schmidt passes of the correction (the subtraction of the first pass
+// fused with the dot products of the second, the second with the norm);
+// its sigma; the new column of the projected matrix.  The correction and
+// its sigma are built before the host sees the residual of that round's
+// Ritz pair, so the round in which a slot converges builds one sigma that
+// is discarded.  Reductions use a block count fixed by the slot's size, so
+// the arithmetic of a slot does not depend on which other slots share its
+// launches.
 #pragma once
 
+#include <atomic>
 #include <chrono>
 #include <vector>
 
@@ -30,34 +35,39 @@ constexpr int kBatchMaxSlots = 64;
 struct BatchSlot {
     Ctx *c = nullptr;
     tbsci_davidson_opts o{};
+    const double *guess = nullptr;  // optional start vector (device)
+    double *out = nullptr;          // optional eigenvector output (device)
+    bool sym = false;               // keep the solve in the C = C^T sector
     int64_t n = 0;
     int nb = 1;    // blocks of this slot in grid-stride launches
     int row = -1;  // row of the scalar area while active
     // device state: basis V / W (each from its pool of n_max + 3 vectors),
-    // the latest Ritz vector kept for a hand-over, FP32 staging, partials
+    // the latest Ritz vector kept for a hand-over or the output, FP32
+    // staging, partial sums
     std::vector<double *> all, vfree, wfree, V, W;
     double *X = nullptr;
     float *f32a = nullptr, *f32b = nullptr;
     double *partial = nullptr;
     size_t bytes = 0;  // device bytes of the above (page-rounded)
     // host state
-    enum { kStart, kHandover, kIter, kDone } phase = kStart;
+    enum { kStart, kHandover, kIter, kFinish, kDone } phase = kStart;
     bool fp32 = false;
     int k = 0;
     std::vector<double> G, y, yprev;
     double theta = 0.0, theta_prev = 0.0, rn = 1e300, best_rn = 1e300;
     int since_best = 0;
     int status = TBSCI_PENDING;
+    const char *msg = "";
     tbsci_davidson_info info{};
     std::chrono::steady_clock::time_point t0;
     void *user = nullptr;  // owner's tag
-    // plan of the current tick
+    // plan of the current round
     struct Plan {
         bool sig32 = false, restart = false, took_xp = false;
-        double *V0 = nullptr, *W0 = nullptr;           // start / hand-over
+        double *V0 = nullptr, *W0 = nullptr;  // start / hand-over
         double *Xn = nullptr, *WXn = nullptr, *T = nullptr, *TW = nullptr;
         double *XP = nullptr, *WXP = nullptr;
-        std::vector<double *> Vb, Wb;                  // basis the new vector joins
+        std::vector<double *> Vb, Wb;  // basis the new vector joins
     } p;
 };
 
@@ -75,10 +85,10 @@ class BatchEngine {
     // free a slot's buffers (not its context); any thread, slot not active
     static void free_slot(BatchSlot *s);
 
-    // the slot joins at the next tick (engine thread)
+    // the slot joins at the next round (engine thread)
     void add(BatchSlot *s);
     size_t active() const { return act_.size(); }
-    // one iteration of every active slot; false if there was none
+    // one round; false if there was no active slot
     bool tick();
     // slots finished since the last call
     std::vector<BatchSlot *> take_done();
@@ -103,5 +113,11 @@ class BatchEngine {
     std::vector<BatchSlot *> act_, done_;
     std::vector<int> free_rows_;
 };
+
+// Solve one problem (guess and out optional, device FP64 [l_alpha][l_beta]);
+// abort, when set, ends the solve at the next round with TBSCI_E_STATE.
+int solve_one(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *out,
+              tbsci_davidson_info &info, hipStream_t st,
+              const std::atomic<bool> *abort = nullptr);
 
 }  // namespace tbsci

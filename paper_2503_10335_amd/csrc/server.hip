@@ -53,7 +53,8 @@ struct Request {
 };
 
 size_t request_bound(const Request &r, bool batched) {
-    const size_t solver = batched ? BatchEngine::slot_bytes(r.n_det, r.o) : davidson_bytes(r.n_det, r.o);
+    (void)batched;  // the batched and the solo solver hold the same state
+    const size_t solver = BatchEngine::slot_bytes(r.n_det, r.o);
     return ctx_bytes_bound(r.M, r.na, r.nb, (int64_t)r.a.size(), (int64_t)r.b.size()) + solver;
 }
 
@@ -154,7 +155,7 @@ struct Server {
                     r->slot->user = r;
                     held += r->slot->bytes;
                 } else {
-                    held += davidson_bytes(r->n_det, r->o);
+                    held += BatchEngine::slot_bytes(r->n_det, r->o);
                 }
                 std::lock_guard<std::mutex> lk(mu);
                 if (held < r->reserved) {  // keep only what the request holds
@@ -286,7 +287,7 @@ struct Server {
             tbsci_davidson_info info{};
             try {
                 if (!st) throw Error(TBSCI_E_DEVICE, "stream creation failed");
-                rc = davidson_run(*r->ctx, r->o, nullptr, nullptr, info, st, &stop);
+                rc = solve_one(*r->ctx, r->o, nullptr, nullptr, info, st, &stop);
                 if (rc == TBSCI_E_STATE) msg = "cancelled";
             } catch (const Error &x) {
                 rc = x.code;
@@ -390,7 +391,7 @@ int tbsci_submit(tbsci_server *srv, int M, int n_alpha, int n_beta, const double
         r->a.assign(alpha, alpha + l_alpha);
         r->b.assign(beta, beta + l_beta);
         r->n_det = l_alpha * l_beta;
-        r->batched = r->n_det <= s->thresh && r->o.n_max <= kBatchMaxVec;
+        r->batched = r->n_det <= s->thresh;
         r->reserved = request_bound(*r, r->batched);
         r->footprint = r->reserved;
         if (r->reserved > s->budget)

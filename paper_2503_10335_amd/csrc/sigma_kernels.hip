@@ -139,7 +139,7 @@ __device__ __forceinline__ int find_desc(const D *__restrict__ d, int nd, int64_
 
 template <typename T, bool ACC>
 __global__ __launch_bounds__(kBlock) void g_row_sweep(const SweepDesc *__restrict__ d, int nd) {
-    const SweepDesc &e = d[find_desc(d, nd, blockIdx.x)];
+    const SweepDesc e = d[find_desc(d, nd, blockIdx.x)];
     row_sweep_block<T, ACC>(blockIdx.x - e.blk0, e.nrows, e.ncols, e.ntiles, e.nrb, e.tpx, e.ptr,
                             e.col, (const T *)e.val, (const T *)e.X, (T *)e.Y);
 }
@@ -184,7 +184,7 @@ struct TransDesc {
 
 template <typename T, bool ADD>
 __global__ __launch_bounds__(kBlock) void g_transpose(const TransDesc *__restrict__ d, int nd) {
-    const TransDesc &e = d[find_desc(d, nd, blockIdx.x)];
+    const TransDesc e = d[find_desc(d, nd, blockIdx.x)];
     transpose_block<T, ADD>(blockIdx.x - e.blk0, e.R, e.Cn, e.ntc, (const T *)e.in, (T *)e.out);
 }
 
@@ -280,7 +280,7 @@ inline AbLds ab_lds(int64_t lb, int kmax, size_t sz, size_t row_sz) {
 
 template <typename T, int KS, int ROW>
 __device__ __forceinline__ void ab_tile_row(const int64_t I, int64_t lb, int P, int nmt,
-                                            const AbLds &L, const int64_t *__restrict__ sa_ptr,
+                                            const AbLds L, const int64_t *__restrict__ sa_ptr,
                                             const Ent *__restrict__ sa_ent,
                                             const int64_t *__restrict__ sb_ptr,
                                             const Ent *__restrict__ sb_grp,
@@ -451,7 +451,7 @@ struct AbDesc {
 template <typename T, int KS, int ROW, int BOUND>
 __global__ __launch_bounds__(BOUND) void g_ab_tile(const AbDesc *__restrict__ d, int nd, int P,
                                                   int nmt) {
-    const AbDesc &e = d[find_desc(d, nd, blockIdx.x)];
+    const AbDesc e = d[find_desc(d, nd, blockIdx.x)];
     ab_tile_row<T, KS, ROW>(blockIdx.x - e.blk0, e.lb, P, nmt, e.L, e.sa_ptr, e.sa_ent, e.sb_ptr,
                             e.sb_grp, e.sb_off, (const T *)e.V, (const T *)e.C, (T *)e.S);
 }
@@ -737,6 +737,10 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
 
 void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, int n,
                         int precision, TableArena &ar, hipStream_t st) {
+    if (n == 1) {  // a group of one: the kernels of a single sigma build
+        launch_sigma(*ctx[0], C[0], S[0], precision, st);
+        return;
+    }
     if (precision == TBSCI_FP64)
         sigma_group_impl<double>(ctx, (const double *const *)C, (double *const *)S, n, ar, st);
     else

@@ -224,13 +224,6 @@ __device__ __forceinline__ void flip_sym_block(int64_t b, int64_t l, double *__r
     }
 }
 
-// abort (optional): checked once per iteration; a set flag ends the solve
-// with TBSCI_E_STATE
-int davidson_run(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *C_out,
-                 tbsci_davidson_info &info, hipStream_t st,
-                 const std::atomic<bool> *abort = nullptr);
-// device bytes davidson_run allocates for n determinants
-size_t davidson_bytes(int64_t n, const tbsci_davidson_opts &o);
 void check_opts(const tbsci_davidson_opts &o);
 
 }  // namespace tbsci

@@ -47,17 +47,34 @@ struct Vals<float> {
 // ---------------------------------------------------------------- sweeps
 
 // Y[I][c] (+)= sum_e val[e] * X[col[e]][c].  Block = 4 waves = 4 output rows
-// x 64 columns; the list of a row is wave-uniform, X rows are read
+// x 64 V columns; the list of a row is wave-uniform, X rows are read
 // coalesced.  Column tiles belong to XCDs round-robin (tile t on XCD t % 8)
 // and an XCD walks its tiles one after the other, so its working set is one
-// panel of X (nrows x 64 columns).
-template <typename T, bool ACC>
+// panel of X (nrows x 64 V columns).
+template <typename T, int V>
+struct Vec;
+template <typename T>
+struct Vec<T, 1> {
+    typedef T type;
+    static __device__ __forceinline__ T zero() { return T(0); }
+};
+template <typename T>
+struct Vec<T, 2> {
+    typedef T type __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ type zero() { return type{T(0), T(0)}; }
+};
+
+// V = columns per lane: 2 when ncols is even (one 16-byte load per lane per
+// nonzero in FP64, so rows start aligned), else 1; a wave covers 64 V
+// columns of its row
+template <typename T, bool ACC, int V>
 __device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_t ncols,
                                                 int64_t ntiles, int64_t nrb, int64_t tiles_per_xcd,
                                                 const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ col,
                                                 const T *__restrict__ val,
                                                 const T *__restrict__ X, T *__restrict__ Y) {
+    using TV = typename Vec<T, V>::type;
     const int64_t xcd = b % kXcd, local = b / kXcd;
     const int64_t tl = local / nrb, rb = local - tl * nrb;
     const int64_t tile = xcd + kXcd * tl;
@@ -66,50 +83,52 @@ __device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_
     const int lane = threadIdx.x & 63;
     const int64_t I = rb * 4 + wave;
     if (I >= nrows) return;
-    const int64_t c = tile * 64 + lane;
-    const bool ok = c < ncols;
-    const T *__restrict__ Xc = X + (ok ? c : 0);
+    const int64_t c = (tile * 64 + lane) * V;
+    const bool ok = c < ncols;  // with V = 2, ncols is even: c + 1 < ncols too
+    const int64_t ld = ncols / V;
+    const TV *__restrict__ Xc = (const TV *)(X + (ok ? c : 0));
     const int64_t e0 = ptr[I], e1 = ptr[I + 1];
-    T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    TV acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = Vec<T, V>::zero();
     int64_t e = e0;
     for (; e + 8 <= e1; e += 8) {
         int32_t j[8];
-        T v[8], x[8];
+        T v[8];
+        TV x[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             j[u] = col[e + u];
             v[u] = val[e + u];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = Xc[(int64_t)j[u] * ncols];
-        acc0 += v[0] * x[0];
-        acc1 += v[1] * x[1];
-        acc2 += v[2] * x[2];
-        acc3 += v[3] * x[3];
-        acc0 += v[4] * x[4];
-        acc1 += v[5] * x[5];
-        acc2 += v[6] * x[6];
-        acc3 += v[7] * x[7];
+        for (int u = 0; u < 8; ++u) x[u] = Xc[(int64_t)j[u] * ld];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u & 3] += v[u] * x[u];
     }
-    for (; e < e1; ++e) acc0 += val[e] * Xc[(int64_t)col[e] * ncols];
-    const T acc = (acc0 + acc1) + (acc2 + acc3);
+    for (; e < e1; ++e) acc[0] += val[e] * Xc[(int64_t)col[e] * ld];
+    const TV a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     if (ok) {
+        TV *y = (TV *)(Y + I * ncols + c);
         if (ACC)
-            Y[I * ncols + c] += acc;
+            *y += a;
         else
-            Y[I * ncols + c] = acc;
+            *y = a;
     }
 }
 
-template <typename T, bool ACC>
+// columns per lane for a sweep of ncols columns
+__host__ __device__ inline int sweep_vec(int64_t ncols) { return ncols % 2 == 0 ? 2 : 1; }
+
+template <typename T, bool ACC, int V>
 __global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t ncols, int64_t ntiles,
                                                       int64_t nrb, int64_t tiles_per_xcd,
                                                       const int64_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const T *__restrict__ val,
                                                       const T *__restrict__ X, T *__restrict__ Y) {
-    row_sweep_block<T, ACC>(blockIdx.x, nrows, ncols, ntiles, nrb, tiles_per_xcd, ptr, col, val, X,
-                            Y);
+    row_sweep_block<T, ACC, V>(blockIdx.x, nrows, ncols, ntiles, nrb, tiles_per_xcd, ptr, col, val,
+                               X, Y);
 }
 
 // Descriptor of one problem in a grouped launch; the problem's blocks are
@@ -140,8 +159,12 @@ __device__ __forceinline__ int find_desc(const D *__restrict__ d, int nd, int64_
 template <typename T, bool ACC>
 __global__ __launch_bounds__(kBlock) void g_row_sweep(const SweepDesc *__restrict__ d, int nd) {
     const SweepDesc e = d[find_desc(d, nd, blockIdx.x)];
-    row_sweep_block<T, ACC>(blockIdx.x - e.blk0, e.nrows, e.ncols, e.ntiles, e.nrb, e.tpx, e.ptr,
-                            e.col, (const T *)e.val, (const T *)e.X, (T *)e.Y);
+    if (sweep_vec(e.ncols) == 2)
+        row_sweep_block<T, ACC, 2>(blockIdx.x - e.blk0, e.nrows, e.ncols, e.ntiles, e.nrb, e.tpx,
+                                   e.ptr, e.col, (const T *)e.val, (const T *)e.X, (T *)e.Y);
+    else
+        row_sweep_block<T, ACC, 1>(blockIdx.x - e.blk0, e.nrows, e.ncols, e.ntiles, e.nrb, e.tpx,
+                                   e.ptr, e.col, (const T *)e.val, (const T *)e.X, (T *)e.Y);
 }
 
 // out[c][r] (+)= in[r][c] for an R x Cn row-major input; 32 x 32 tiles via LDS.
@@ -475,15 +498,14 @@ T *workspace(Ctx &c, int which) {
 template <typename T>
 void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st) {
     const int64_t nrows = s.l;
-    const int64_t ntiles = (ncols + 63) / 64, nrb = (nrows + 3) / 4;
+    const int vec = sweep_vec(ncols);
+    const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec), nrb = (nrows + 3) / 4;
     const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
     const unsigned grid = (unsigned)(kXcd * tpx * nrb);
-    if (acc)
-        k_row_sweep<T, true><<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr, s.a_col,
-                                                      Vals<T>::a(s), X, Y);
-    else
-        k_row_sweep<T, false><<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr,
-                                                       s.a_col, Vals<T>::a(s), X, Y);
+    auto f = vec == 2 ? (acc ? k_row_sweep<T, true, 2> : k_row_sweep<T, false, 2>)
+                      : (acc ? k_row_sweep<T, true, 1> : k_row_sweep<T, false, 1>);
+    f<<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr, s.a_col, Vals<T>::a(s), X,
+                               Y);
     TB_HIP(hipGetLastError());
 }
 
@@ -659,7 +681,8 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
     int64_t bsa = 0, bsb = 0, bt1 = 0, bt2 = 0;
     auto sweep = [&](std::vector<SweepDesc> &v, int64_t &blk, const Spin &s, int64_t ncols,
                      const T *X, T *Y) {
-        const int64_t ntiles = (ncols + 63) / 64, nrb = (s.l + 3) / 4;
+        const int vec = sweep_vec(ncols);
+        const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec), nrb = (s.l + 3) / 4;
         const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
         v.push_back(SweepDesc{blk, s.l, ncols, ntiles, nrb, tpx, s.a_ptr, s.a_col, Vals<T>::a(s),
                               X, Y});

@@ -223,3 +223,30 @@ def test_davidson_mixed(env, name):
     assert info["iters_fp32"] > 0 and info["iters_fp64"] > 0
     assert abs(info["energy"] - ref["energy"]) < 1e-6
     ctx.close()
+
+
+def test_davidson_guess_and_vector(env):
+    """A start vector from the caller: the converged eigenvector as guess
+    converges at once to the same energy; a zero guess is rejected; the
+    returned vector has unit norm, its largest entry positive, and the
+    oracle residual of the stated energy."""
+    T, O, torch = env
+    p = PROBS["ranked_m12"]
+    ctx = T.Context.from_problem(p)
+    sp = O.Space.of(p)
+    info, X = ctx.davidson(tol_resid=1e-9, n_max=8, max_iter=400)
+    assert info["status"] == 0
+    x = X.cpu().numpy().ravel()
+    assert abs(np.linalg.norm(x) - 1) < 1e-12
+    k = int(np.argmax(np.abs(x)))
+    assert x[k] > 0
+    assert np.linalg.norm(sp.sigma(x).ravel() - info["energy"] * x) < 5e-9
+    # warm start (scaled, to exercise the normalisation of the guess)
+    info2, X2 = ctx.davidson(tol_resid=1e-9, n_max=8, guess=3.0 * X)
+    assert info2["status"] == 0 and info2["iters"] <= 3
+    assert abs(info2["energy"] - info["energy"]) < 1e-10
+    assert np.abs(X2.cpu().numpy() - X.cpu().numpy()).max() < 1e-8
+    with pytest.raises(T.TbsciError) as ei:
+        ctx.davidson(guess=torch.zeros_like(X))
+    assert ei.value.code == T.TBSCI_E_INVAL and "zero" in str(ei.value)
+    ctx.close()

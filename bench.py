@@ -128,6 +128,28 @@ def summarize(trace_dir, fetch_dir, write_dir, out, commands):
     print("\n".join(lines))
 
 
+def summarize_trace(trace_dir, out, commands, title):
+    """Short text summary of one rocprofv3 kernel-trace csv run."""
+    import csv
+    import glob
+    got = glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))
+    if len(got) != 1:
+        raise SystemExit(f"expected one kernel_stats.csv in {trace_dir}, found {got}")
+    stats = list(csv.DictReader(open(got[0])))
+    lines = [f"# rocprofv3 summary: {title}", "# commands (run from the repository root):"]
+    lines += [f"#   {c}" for c in commands]
+    lines.append(f"#   python3 bench.py --summarize-trace {trace_dir} --summary-out "
+                 f"{os.path.relpath(out, ROOT)} (with the command above as --command)")
+    lines += ["", f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in stats[:25]:
+        lines.append(f"{short_name(r['Name'])[:40]:40s} {int(r['Calls']):6d} "
+                     f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['TotalDurationNs']) / 1e6:10.2f} "
+                     f"{float(r['Percentage']):6.2f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def measured_traffic(label: str, prec: str):
     """HBM bytes per launch from the committed counter summary, or None when
     there is none or the kernel source changed since it was taken."""
@@ -168,6 +190,9 @@ def parse():
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarize three rocprofv3 csv runs of this benchmark into "
                          "the profile summary and exit (no GPU)")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="summarize one rocprofv3 kernel-trace csv run and exit (no GPU)")
+    ap.add_argument("--title", default="kernel trace")
     ap.add_argument("--summary-out", default=PROFILE)
     ap.add_argument("--command", action="append", default=[],
                     help="command line recorded in the summary (repeatable)")
@@ -178,6 +203,9 @@ def main():
     args = parse()
     if args.summarize:
         summarize(*args.summarize, args.summary_out, args.command)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.summary_out, args.command, args.title)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

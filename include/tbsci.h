@@ -169,11 +169,11 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
  * to the host, with one host synchronisation per iteration (the correction
  * and its sigma are built before the host sees that iteration's residual,
  * so a converged solve has built one sigma more than it used; info.iters
- * counts it).  Allocates its workspace ((2 n_max + 6) FP64 vectors, plus
+ * counts it).  Allocates its workspace ((2 n_max + 7) FP64 vectors, plus
  * two FP32 vectors for MIXED): the basis V and its images H V, the Ritz
- * vector and its image, the correction and its image, and the previous
- * Ritz direction with its image, which the restart keeps next to the Ritz
- * vector.
+ * vector and its image, the correction and its image, the previous Ritz
+ * direction with its image, which the restart keeps next to the Ritz
+ * vector, and the diagonal H_KK (Sec. II.C: computed once and stored).
  */
 int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double *guess_dev,
                    double *C_out_dev, tbsci_davidson_info *info, void *stream);
@@ -203,7 +203,7 @@ int tbsci_sigma_batch(tbsci_ctx *const *ctxs, int n, const void *const *C_dev,
  * array of n.  infos[i] and status[i] (TBSCI_OK or
  * TBSCI_E_NOTCONV) receive problem i's result.  The start vector is that
  * of tbsci_davidson without a guess.  Eigenvectors are not
- * returned.  Each problem holds (2 n_max + 6) FP64 vectors, plus two FP32
+ * returned.  Each problem holds (2 n_max + 7) FP64 vectors, plus two FP32
  * vectors for TBSCI_MIXED, while it runs.  Returns TBSCI_OK when every
  * problem ran (whatever its own status), else an error code.
  */

@@ -249,8 +249,15 @@ __global__ __launch_bounds__(kB) void gv_signed_copy(const VDesc *__restrict__ d
     TB_SLOT_LOOP(e, lb, t) e.o0[t] = s * e.in[t];
 }
 
+// o0 = H_KK for every determinant of the slot (stored for the whole solve)
+__global__ __launch_bounds__(kB) void gv_diag(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    TB_SLOT_LOOP(e, lb, t) e.o0[t] = diag_at(e, t);
+}
+
 // x = V y, wx = W y, t = (wx - theta x) / (theta - H_KK) with a floor;
-// partial sums of |wx - theta x|^2
+// partial sums of |wx - theta x|^2 (H_KK read from the stored diagonal)
 __global__ __launch_bounds__(kB) void gv_ritz(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
@@ -265,7 +272,7 @@ __global__ __launch_bounds__(kB) void gv_ritz(const VDesc *__restrict__ d, int n
             }
         const double r = wv - e.theta * xv;
         acc[0] += r * r;
-        double den = e.theta - diag_at(e, t);
+        double den = e.theta - e.in[t];
         if (fabs(den) < e.floor_) den = den < 0.0 ? -e.floor_ : e.floor_;
         e.o0[t] = xv;
         e.o1[t] = wv;
@@ -428,6 +435,7 @@ __global__ __launch_bounds__(kB) void gv_to_f64(const VDesc *__restrict__ d, int
 // operations of a round, in issue order (a slot uses a subsequence)
 enum Op {
     O_AMAX, O_AMAX_S, O_OUT,                        // finish: signed copy to the output
+    O_DIAG,                                         // start: the stored diagonal
     O_FILL, O_DMIN, O_AMIN,                         // start on the smallest H_KK
     O_GCOPY, O_GN_D, O_GN_R, O_GN_S,                // start from a guess
     O_RITZ, O_RITZ_R, O_SYM,                        // Ritz pair, residual, correction
@@ -442,7 +450,7 @@ enum Op {
 };
 
 enum Kind {
-    K_FILL, K_COPY, K_DMIN, K_AMIN, K_AMAX, K_ASIGN, K_SCOPY, K_RITZ, K_RED, K_SYM, K_LC,
+    K_DIAG, K_FILL, K_COPY, K_DMIN, K_AMIN, K_AMAX, K_ASIGN, K_SCOPY, K_RITZ, K_RED, K_SYM, K_LC,
     K_DOT, K_SUB, K_SUBDOT, K_SUBNORM, K_SCALE, K_F32, K_F64, K_NONE
 };
 
@@ -451,6 +459,7 @@ Kind kind_of(int op) {
         case O_AMAX: return K_AMAX;
         case O_AMAX_S: return K_ASIGN;
         case O_OUT: return K_SCOPY;
+        case O_DIAG: return K_DIAG;
         case O_FILL: return K_FILL;
         case O_DMIN: return K_DMIN;
         case O_AMIN: return K_AMIN;
@@ -504,7 +513,7 @@ BatchEngine::~BatchEngine() {
 
 size_t BatchEngine::slot_bytes(int64_t n, const tbsci_davidson_opts &o) {
     const size_t v = page(8 * (size_t)n);
-    size_t b = 2 * (size_t)(o.n_max + 3) * v + page(8 * (size_t)kSV * kNbMax);
+    size_t b = (2 * (size_t)(o.n_max + 3) + 1) * v + page(8 * (size_t)kSV * kNbMax);
     if (o.precision == TBSCI_MIXED) b += 2 * page(4 * (size_t)n);
     return b;
 }
@@ -528,6 +537,7 @@ BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o) {
             s->vfree.push_back((double *)get(8 * (size_t)s->n));
             s->wfree.push_back((double *)get(8 * (size_t)s->n));
         }
+        s->diag = (double *)get(8 * (size_t)s->n);
         s->partial = (double *)get(8 * (size_t)kSV * kNbMax);
         if (o.precision == TBSCI_MIXED) {
             s->f32a = (float *)get(4 * (size_t)s->n);
@@ -649,6 +659,12 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
     const double *sig_in = nullptr;
     double *sig_out = nullptr;
     if (s.phase == BatchSlot::kStart || s.phase == BatchSlot::kHandover) {
+        if (s.phase == BatchSlot::kStart) {
+            VDesc dg = base();
+            diag_fields(dg);
+            dg.o0 = s.diag;
+            S.ops[O_DIAG].push_back(dg);
+        }
         if (s.phase == BatchSlot::kStart && !s.guess) {
             P.V0 = take(s.vfree);
             VDesc f = base();
@@ -713,6 +729,7 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         }
         r.theta = s.theta;
         r.floor_ = s.o.precond_floor;
+        r.in = s.diag;
         r.o0 = P.Xn;
         r.o1 = P.WXn;
         r.o2 = P.T;
@@ -863,6 +880,7 @@ bool BatchEngine::tick() {
         const int nd = (int)S.ops[op].size();
         const VDesc *d = dev[op];
         switch (kind_of(op)) {
+            case K_DIAG: gv_diag<<<g, kB, 0, st_>>>(d, nd); break;
             case K_FILL: gv_fill<<<g, kB, 0, st_>>>(d, nd); break;
             case K_COPY: gv_copy<<<g, kB, 0, st_>>>(d, nd); break;
             case K_DMIN: gv_diag_min<<<g, kB, 0, st_>>>(d, nd); break;

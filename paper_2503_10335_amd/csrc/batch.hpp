@@ -42,10 +42,11 @@ struct BatchSlot {
     int nb = 1;    // blocks of this slot in grid-stride launches
     int row = -1;  // row of the scalar area while active
     // device state: basis V / W (each from its pool of n_max + 3 vectors),
-    // the latest Ritz vector kept for a hand-over or the output, FP32
-    // staging, partial sums
+    // the latest Ritz vector kept for a hand-over or the output, the
+    // diagonal, FP32 staging, partial sums
     std::vector<double *> all, vfree, wfree, V, W;
     double *X = nullptr;
+    double *diag = nullptr;  // H_KK, computed in the start round
     float *f32a = nullptr, *f32b = nullptr;
     double *partial = nullptr;
     size_t bytes = 0;  // device bytes of the above (page-rounded)

@@ -353,47 +353,6 @@ __global__ void k_full_diag(const uint64_t *__restrict__ astr, int64_t la, int64
     out[k] = v;
 }
 
-// per-block (min value, first index) of the diagonal, computed on the fly
-__global__ __launch_bounds__(kBlock) void k_diag_argmin(
-    const uint64_t *__restrict__ astr, int64_t la, int64_t lb, int M,
-    const double *__restrict__ da, const double *__restrict__ db, const double *__restrict__ jb,
-    double *__restrict__ pv, int64_t *__restrict__ pi) {
-    __shared__ double sv[kBlock];
-    __shared__ int64_t si[kBlock];
-    const int64_t n = la * lb;
-    double best = 1e308;
-    int64_t bi = -1;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * kBlock) {
-        const int64_t ia = k / lb, ib = k - ia * lb;
-        double v = da[ia] + db[ib];
-        const double *jr = jb + ib * M;
-        for (uint64_t x = astr[ia]; x; x &= x - 1) v += jr[__builtin_ctzll(x)];
-        if (v < best) {  // k increases along the loop: keeps the first minimum
-            best = v;
-            bi = k;
-        }
-    }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            const double v2 = sv[threadIdx.x + off];
-            const int64_t i2 = si[threadIdx.x + off];
-            if (i2 >= 0 && (v2 < sv[threadIdx.x] ||
-                            (v2 == sv[threadIdx.x] && (si[threadIdx.x] < 0 || i2 < si[threadIdx.x])))) {
-                sv[threadIdx.x] = v2;
-                si[threadIdx.x] = i2;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        pv[blockIdx.x] = sv[0];
-        pi[blockIdx.x] = si[0];
-    }
-}
 
 template <typename T>
 T *dalloc(size_t n) {
@@ -484,10 +443,5 @@ void launch_full_diag(const Ctx &c, double *out, hipStream_t st) {
     TB_HIP(hipGetLastError());
 }
 
-void launch_diag_argmin(const Ctx &c, double *pv, int64_t *pi, int nblk, hipStream_t st) {
-    k_diag_argmin<<<nblk, kBlock, 0, st>>>(c.sp[0].str, c.sp[0].l, c.sp[1].l, c.M, c.sp[0].dsame,
-                                           c.sp[1].dsame, c.sp[1].jocc, pv, pi);
-    TB_HIP(hipGetLastError());
-}
 
 }  // namespace tbsci

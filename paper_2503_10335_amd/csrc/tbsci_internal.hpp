@@ -186,7 +186,6 @@ void check_dev(const void *p, int device, const char *name);
 void build_spin(Ctx &c, Spin &s, const uint64_t *host_str, hipStream_t st);
 void launch_lookup(const Spin &s, const uint64_t *q, int64_t n, int32_t *out, hipStream_t st);
 void launch_full_diag(const Ctx &c, double *out, hipStream_t st);
-void launch_diag_argmin(const Ctx &c, double *part_val, int64_t *part_idx, int nblk, hipStream_t st);
 
 // ---- launchers (sigma_kernels.hip)
 void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms = 7);

@@ -254,8 +254,9 @@ struct Mfma<float> {
 //
 // ROW selects where the output row accumulates: an FP64 row in LDS (FP64
 // LDS atomics, also for FP32 sigma: on gfx950 they are several times faster
-// than FP32 LDS atomics, and the row is rounded once at the end), a row of
-// type T in LDS, or sigma itself through global atomics.
+// than FP32 LDS atomics, and the row is rounded once at the end) for as many
+// beta strings as fit, the rest through global atomics on sigma; or, for an
+// FP32 row too long for that, a whole row of type T in LDS.
 #ifndef TB_AB_TW
 #define TB_AB_TW 32
 #endif
@@ -280,13 +281,22 @@ __device__ __forceinline__ auto pick4(const V4 &v, int r) {
     return r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
 }
 
-enum { kRowF64 = 0, kRowT = 1, kRowGlobal = 2 };
+// Where the output row accumulates: kRowF64, a whole FP64 row in LDS;
+// kRowSplit, an FP64 row in LDS for the first nrow beta strings, the links
+// to strings beyond nrow going to sigma through global atomics; kRowT, a
+// whole row of type T in LDS
+enum { kRowF64 = 0, kRowT = 1, kRowSplit = 2 };
 
 struct AbLds {
     size_t row, aj, x, total;
+    int64_t nrow;  // row entries held in LDS
 };
 
-inline AbLds ab_lds(int64_t lb, int kmax, size_t sz, size_t row_sz) {
+constexpr size_t kLdsMax = 160 * 1024;
+
+// layout for a row of `nrow` entries of row_sz bytes (nrow < 0: as many as
+// fit in kLdsMax, at most lb)
+inline AbLds ab_lds(int64_t lb, int kmax, size_t sz, size_t row_sz, int64_t nrow = -1) {
     AbLds L{};
     size_t o = 0;
     auto take = [&](size_t n) {
@@ -294,9 +304,14 @@ inline AbLds ab_lds(int64_t lb, int kmax, size_t sz, size_t row_sz) {
         o += (n + 15) & ~size_t(15);
         return at;
     };
-    L.row = take((size_t)lb * row_sz);
     L.aj = take((size_t)kmax * 4);
     L.x = take(2 * (size_t)kmax * kXS * sz);
+    if (nrow < 0) {
+        const size_t room = o < kLdsMax ? (kLdsMax - o) / row_sz : 0;
+        nrow = std::min<int64_t>(lb, (int64_t)(room & ~size_t(1)));
+    }
+    L.nrow = nrow;
+    L.row = take((size_t)nrow * row_sz);
     L.total = o;
     return L;
 }
@@ -311,8 +326,8 @@ __device__ __forceinline__ void ab_tile_row(const int64_t I, int64_t lb, int P, 
                                             const T *__restrict__ V, const T *__restrict__ C,
                                             T *__restrict__ S) {
     using M = Mfma<T>;
-    using R = typename std::conditional<ROW == kRowF64, double, T>::type;
-    constexpr bool LDS_ROW = ROW != kRowGlobal;
+    using R = typename std::conditional<ROW == kRowT, T, double>::type;
+    const int64_t nrow = ROW == kRowSplit ? L.nrow : lb;
     extern __shared__ __align__(16) unsigned char smem[];
     R *row = (R *)(smem + L.row);
     int32_t *aj = (int32_t *)(smem + L.aj);
@@ -328,8 +343,7 @@ __device__ __forceinline__ void ab_tile_row(const int64_t I, int64_t lb, int P, 
     const int ng = 4 * nmt;
     const int key = 4 * wave + g;  // this lane's link group
 
-    if (LDS_ROW)
-        for (int64_t i = tid; i < lb; i += nthr) row[i] = R(0);
+    for (int64_t i = tid; i < nrow; i += nthr) row[i] = R(0);
     for (int k = tid; k < Kp; k += nthr) aj[k] = k < K ? sa_ent[a0 + k].j : -1;
 
     // A fragments: lane holds U[k = 4 ks + g][row cl] of this wave's M-tile
@@ -432,7 +446,7 @@ __device__ __forceinline__ void ab_tile_row(const int64_t I, int64_t lb, int P, 
                 const Ent e = sb_grp[eb[ns] + x];
                 T v = pick4(acc[ns], (int)(((e.o >> 16) & 15) >> 2));
                 if ((e.o >> 12) & 1u) v = -v;
-                if (LDS_ROW)
+                if (ROW != kRowSplit || e.j < nrow)
                     atomicAdd(&row[e.j], (R)v);
                 else
                     atomicAdd(&S[I * lb + e.j], v);
@@ -441,8 +455,8 @@ __device__ __forceinline__ void ab_tile_row(const int64_t I, int64_t lb, int P, 
         if (t + 1 < ntile) store_x(xbuf + (size_t)((t + 1) & 1) * Kp * kXS);
         __syncthreads();
     }
-    if (LDS_ROW)
-        for (int64_t i = tid; i < lb; i += nthr) S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
+    // (the strings from nrow on received their links by global atomics)
+    for (int64_t i = tid; i < nrow; i += nthr) S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
 }
 
 template <typename T, int KS, int ROW, int BOUND>
@@ -524,24 +538,24 @@ void allow_lds(Ctx &c, const void *f, size_t bytes) {
     c.lds_set.emplace_back(f, bytes);
 }
 
-constexpr size_t kLdsMax = 160 * 1024;
-
 template <typename T, int KS, int BOUND>
 void launch_ab_kb(Ctx &c, const T *C, T *S, hipStream_t st) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     const int P = c.P, nmt = (P + 15) / 16;
-    int row = kRowGlobal;
-    AbLds L = ab_lds(B.l, 4 * KS, sizeof(T), 0);
-    if (ab_lds(B.l, 4 * KS, sizeof(T), 8).total <= kLdsMax) {
-        row = kRowF64;
-        L = ab_lds(B.l, 4 * KS, sizeof(T), 8);
-    } else if (sizeof(T) < 8 && ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T)).total <= kLdsMax) {
-        row = kRowT;
-        L = ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T));
+    // an FP64 row (split when the whole row does not fit); FP32 sigma with
+    // a long row keeps a whole FP32 row instead when that fits
+    int row = kRowF64;
+    AbLds L = ab_lds(B.l, 4 * KS, sizeof(T), 8);
+    if (L.nrow < B.l) {
+        row = kRowSplit;
+        if (sizeof(T) < 8 && ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T), B.l).total <= kLdsMax) {
+            row = kRowT;
+            L = ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T), B.l);
+        }
     }
     auto f = row == kRowF64 ? k_ab_tile<T, KS, kRowF64, BOUND>
              : row == kRowT ? k_ab_tile<T, KS, kRowT, BOUND>
-                            : k_ab_tile<T, KS, kRowGlobal, BOUND>;
+                            : k_ab_tile<T, KS, kRowSplit, BOUND>;
     if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
     f<<<(unsigned)A.l, 64 * nmt, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
                                                 B.g_ent, B.g_off, Vals<T>::V(c), C, S);
@@ -713,7 +727,7 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
         trans(t2, bt2, B.l, A.l, St, S[i]);
         const int KS = ab_ks(c);
         const AbLds L = ab_lds(B.l, 4 * std::max(KS, 1), sizeof(T), 8);
-        if (KS == 0 || L.total > kLdsMax) {
+        if (KS == 0 || L.nrow < B.l) {  // grouped kernels hold whole FP64 rows
             direct.push_back(i);
             continue;
         }
@@ -745,8 +759,9 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
     for (size_t k = 0; k < groups.size(); ++k)
         launch_ab_group<T>(dg[k], (int)groups[k].d.size(), groups[k].blocks, groups[k].P,
                            groups[k].KS, groups[k].lds, *ctx[0], st);
-    for (int i : direct) {
+    for (int i : direct) {  // single-problem opposite-spin kernels
         Ctx &c = *ctx[i];
+        if (launch_ab<T>(c, C[i], S[i], st)) continue;
         const Spin &A = c.sp[0], &B = c.sp[1];
         const int64_t ncb = (B.l + kBlock - 1) / kBlock;
         k_ab_direct<T><<<(unsigned)(A.l * ncb), kBlock, 0, st>>>(B.l, ncb, c.P, A.s_ptr, A.s_ent,

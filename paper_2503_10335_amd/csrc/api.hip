@@ -70,8 +70,9 @@ T *dalloc(size_t n) {
 }
 
 void free_spin(Spin &s) {
-    void *ptrs[] = {s.str,   s.keys,  s.pos,     s.s_ptr, s.s_ent, s.d_ptr, s.d_ent, s.a_ptr,
-                    s.a_col, s.a_val, s.a_val32, s.dsame, s.jocc,  s.g_ent, s.g_off};
+    void *ptrs[] = {s.str,   s.keys,  s.pos,     s.s_ptr, s.s_ent, s.d_ptr, s.d_ent,
+                    s.a_ptr, s.a_col, s.a_val,   s.a_val32, s.dsame, s.jocc,  s.g_ent,
+                    s.g_off, s.b_off, s.b_col,   s.b_val, s.b_val32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     s = Spin{};
@@ -154,10 +155,14 @@ size_t spin_bytes(int M, int P, int n, int64_t l, int64_t n_s, int64_t n_d) {
     const size_t L = (size_t)l;
     const int64_t n_a = l + (n_s - (int64_t)n * l) + n_d;
     const size_t ngroup = 4 * (size_t)((P + 15) / 16);
+    const size_t nch = (size_t)((l + kSweepChunk - 1) / kSweepChunk);
+    const size_t chunked = nch > 1 ? page(4 * L * (nch + 1)) + page(4 * (size_t)n_a) +
+                                         page(8 * (size_t)n_a) + page(4 * (size_t)n_a)
+                                   : 0;
     return page(8 * L) * 2 + page(4 * L) + page(8 * L) + page(8 * (L + 1)) * 3 +
            page(8 * (size_t)n_s) * 2 + page(4 * L * (ngroup + 1)) + page(8 * (size_t)n_d) +
            page(8 * L) + page(8 * L * (size_t)M) + page(4 * (size_t)n_a) +
-           page(8 * (size_t)n_a) + page(4 * (size_t)n_a);
+           page(8 * (size_t)n_a) + page(4 * (size_t)n_a) + chunked;
 }
 
 size_t fixed_bytes(int M, int P, int64_t l_alpha, int64_t l_beta) {

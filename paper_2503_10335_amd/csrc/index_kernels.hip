@@ -340,6 +340,33 @@ __global__ void k_group_by_tile(const int64_t *__restrict__ s_ptr, const Ent *__
     // off[t + 1] advanced to the end of group t = start of group t + 1
 }
 
+// Same-spin rows regrouped by source chunk (col / chunk), stable within a
+// chunk; off[row (nch + 1) + c] = start of chunk c relative to the row.
+__global__ void k_chunk_rows(const int64_t *__restrict__ a_ptr, const int32_t *__restrict__ a_col,
+                             const double *__restrict__ a_val, const float *__restrict__ a_val32,
+                             int64_t l, int nch, int64_t chunk, int32_t *__restrict__ off,
+                             int32_t *__restrict__ b_col, double *__restrict__ b_val,
+                             float *__restrict__ b_val32) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= l) return;
+    const int64_t b = a_ptr[row], e = a_ptr[row + 1];
+    int32_t *o = off + row * (nch + 1);
+    for (int c = 0; c <= nch; ++c) o[c] = 0;
+    for (int64_t i = b; i < e; ++i) o[a_col[i] / chunk + 1]++;
+    for (int c = 0; c < nch; ++c) o[c + 1] += o[c];
+    // o[c] = start of chunk c; place with running cursors kept in o[c], then
+    // shift back
+    for (int64_t i = b; i < e; ++i) {
+        const int c = (int)(a_col[i] / chunk);
+        const int64_t at = b + o[c]++;
+        b_col[at] = a_col[i];
+        b_val[at] = a_val[i];
+        b_val32[at] = a_val32[i];
+    }
+    for (int c = nch; c > 0; --c) o[c] = o[c - 1];
+    o[0] = 0;
+}
+
 // H_KK = d_alpha(I) + d_beta(I') + sum_{p in I} jocc_beta[I'][p]
 __global__ void k_full_diag(const uint64_t *__restrict__ astr, int64_t la, int64_t lb, int M,
                             const double *__restrict__ da, const double *__restrict__ db,
@@ -425,6 +452,17 @@ void build_spin(Ctx &c, Spin &s, const uint64_t *host_str, hipStream_t st) {
     k_same_spin<<<wblocks, kBlock, 0, st>>>(s.str, l, M, c.h, c.eri, s.s_ptr, s.s_ent, s.d_ptr,
                                              s.d_ent, s.dsame, s.a_ptr, s.a_col, s.a_val, s.a_val32);
     TB_HIP(hipGetLastError());
+    s.nch = (int)((l + kSweepChunk - 1) / kSweepChunk);
+    if (s.nch > 1) {
+        s.b_off = dalloc<int32_t>((size_t)l * (s.nch + 1));
+        s.b_col = dalloc<int32_t>(s.n_a);
+        s.b_val = dalloc<double>(s.n_a);
+        s.b_val32 = dalloc<float>(s.n_a);
+        k_chunk_rows<<<blocks_for(l, 128), 128, 0, st>>>(s.a_ptr, s.a_col, s.a_val, s.a_val32, l,
+                                                          s.nch, kSweepChunk, s.b_off, s.b_col,
+                                                          s.b_val, s.b_val32);
+        TB_HIP(hipGetLastError());
+    }
     TB_HIP(hipStreamSynchronize(st));
     TB_HIP(hipFree(cnt));
 }

@@ -36,11 +36,13 @@ struct Vals;
 template <>
 struct Vals<double> {
     static const double *a(const Spin &s) { return s.a_val; }
+    static const double *b(const Spin &s) { return s.b_val; }
     static const double *V(const Ctx &c) { return c.V64; }
 };
 template <>
 struct Vals<float> {
     static const float *a(const Spin &s) { return s.a_val32; }
+    static const float *b(const Spin &s) { return s.b_val32; }
     static const float *V(const Ctx &c) { return c.V32; }
 };
 
@@ -73,7 +75,9 @@ __device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_
                                                 const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ col,
                                                 const T *__restrict__ val,
-                                                const T *__restrict__ X, T *__restrict__ Y) {
+                                                const T *__restrict__ X, T *__restrict__ Y,
+                                                const int32_t *__restrict__ chk = nullptr,
+                                                int nch = 1, int ch = 0) {
     using TV = typename Vec<T, V>::type;
     const int64_t xcd = b % kXcd, local = b / kXcd;
     const int64_t tl = local / nrb, rb = local - tl * nrb;
@@ -87,7 +91,13 @@ __device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_
     const bool ok = c < ncols;  // with V = 2, ncols is even: c + 1 < ncols too
     const int64_t ld = ncols / V;
     const TV *__restrict__ Xc = (const TV *)(X + (ok ? c : 0));
-    const int64_t e0 = ptr[I], e1 = ptr[I + 1];
+    // the row's entries (of source chunk ch when the rows are chunked)
+    int64_t e0 = ptr[I], e1 = ptr[I + 1];
+    if (chk) {
+        const int32_t *o = chk + I * (nch + 1) + ch;
+        e1 = e0 + o[1];
+        e0 += o[0];
+    }
     TV acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = Vec<T, V>::zero();
@@ -126,9 +136,11 @@ __global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t nco
                                                       const int64_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const T *__restrict__ val,
-                                                      const T *__restrict__ X, T *__restrict__ Y) {
+                                                      const T *__restrict__ X, T *__restrict__ Y,
+                                                      const int32_t *__restrict__ chk, int nch,
+                                                      int ch) {
     row_sweep_block<T, ACC, V>(blockIdx.x, nrows, ncols, ntiles, nrb, tiles_per_xcd, ptr, col, val,
-                               X, Y);
+                               X, Y, chk, nch, ch);
 }
 
 // Descriptor of one problem in a grouped launch; the problem's blocks are
@@ -509,6 +521,9 @@ T *workspace(Ctx &c, int which) {
     return (T *)c.work + which * nd;
 }
 
+// Y (+)= A_s X.  With more than one source chunk, one pass per chunk (the
+// first one writes unless acc), so that the X rows an XCD gathers in a pass
+// stay in its L2.
 template <typename T>
 void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st) {
     const int64_t nrows = s.l;
@@ -516,11 +531,17 @@ void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, 
     const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec), nrb = (nrows + 3) / 4;
     const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
     const unsigned grid = (unsigned)(kXcd * tpx * nrb);
-    auto f = vec == 2 ? (acc ? k_row_sweep<T, true, 2> : k_row_sweep<T, false, 2>)
-                      : (acc ? k_row_sweep<T, true, 1> : k_row_sweep<T, false, 1>);
-    f<<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr, s.a_col, Vals<T>::a(s), X,
-                               Y);
-    TB_HIP(hipGetLastError());
+    const bool chunked = s.nch > 1;
+    for (int ch = 0; ch < s.nch; ++ch) {
+        const bool a = acc || ch > 0;
+        auto f = vec == 2 ? (a ? k_row_sweep<T, true, 2> : k_row_sweep<T, false, 2>)
+                          : (a ? k_row_sweep<T, true, 1> : k_row_sweep<T, false, 1>);
+        f<<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr,
+                                   chunked ? s.b_col : s.a_col,
+                                   chunked ? Vals<T>::b(s) : Vals<T>::a(s), X, Y,
+                                   chunked ? s.b_off : nullptr, s.nch, ch);
+        TB_HIP(hipGetLastError());
+    }
 }
 
 template <typename T, bool ADD>

@@ -57,6 +57,14 @@ struct Spin {
     int32_t *a_col = nullptr;
     double *a_val = nullptr;
     float *a_val32 = nullptr;
+    // the same rows grouped by source chunk (chunks of kSweepChunk strings)
+    // for the L2-blocked sweep, when there is more than one chunk:
+    // row I's entries with col in chunk c are b_*[a_ptr[I] + b_off[I (nch + 1) + c] ...]
+    int nch = 1;
+    int32_t *b_off = nullptr;
+    int32_t *b_col = nullptr;
+    double *b_val = nullptr;
+    float *b_val32 = nullptr;
     double *dsame = nullptr;   // [l] diagonal of the same-spin operator
     double *jocc = nullptr;    // [l][M]: sum_{r in I} (pp|rr) for each p
     int64_t n_s = 0, n_d = 0, n_a = 0;
@@ -67,6 +75,10 @@ struct Spin {
     Ent *g_ent = nullptr;
     int32_t *g_off = nullptr;
 };
+
+// Sweep source chunk: the gathered rows of one chunk, 128 columns wide in
+// FP64, fill 3 MB of an XCD's 4 MB L2
+constexpr int64_t kSweepChunk = 3072;
 
 struct Ctx {
     int M = 0, P = 0, device = 0;

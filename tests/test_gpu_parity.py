@@ -250,3 +250,23 @@ def test_davidson_guess_and_vector(env):
         ctx.davidson(guess=torch.zeros_like(X))
     assert ei.value.code == T.TBSCI_E_INVAL and "zero" in str(ei.value)
     ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(3200, 40), (40, 3200)])
+def test_sigma_chunked_sweeps(env, shape):
+    """More than 3072 strings of one spin: that spin's same-spin sweep runs
+    in source chunks (one pass per chunk of 3072 strings); FP64 and FP32
+    sigma against the oracle."""
+    T, O, torch = env
+    la, lb = shape
+    p = W.random_selection(14, 7, 7, la, lb, seed=31)
+    ctx = T.Context.from_problem(p)
+    C = np.random.default_rng(5).normal(size=(la, lb))
+    ref = O.Space.of(p).sigma(C, nthreads=16)
+    Cg = torch.from_numpy(C).cuda()
+    got = ctx.sigma(Cg).cpu().numpy()
+    e, m = _rel(got, ref)
+    assert e <= 1e-12 and m <= 1e-12
+    got32 = ctx.sigma(Cg.float(), precision=T.TBSCI_FP32).double().cpu().numpy()
+    assert _rel(got32, ref)[0] <= 2e-5
+    ctx.close()

@@ -35,6 +35,8 @@ PEAK = {  # MI355X published peaks
 PROFILE = os.path.join(ROOT, "profiles", "sigma_kernels_sel_m16.txt")
 SIGMA_SRC = os.path.join(ROOT, "paper_2503_10335_amd", "csrc", "sigma_kernels.hip")
 KERNEL_LABEL = {  # kernel-name prefix in the profiler -> (timing name, precision)
+    "k_ab_slab<double": ("opposite_spin", "fp64"),
+    "k_ab_slab<float": ("opposite_spin", "fp32"),
     "k_ab_tile<double": ("opposite_spin", "fp64"),
     "k_ab_tile<float": ("opposite_spin", "fp32"),
     "k_ab_direct<double": ("opposite_spin", "fp64"),
@@ -174,6 +176,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sel_m16")
     ap.add_argument("--no-davidson", action="store_true")
+    ap.add_argument("--no-davidson-ref", action="store_true",
+                    help="skip the FP64 reference solve to |r| <= 1e-6 (for spaces where it "
+                         "takes too long); the mixed energy is then compared with the FP64 one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
@@ -336,28 +341,37 @@ def main():
     }
 
     if not args.no_davidson:
-        ref, _ = ctx.davidson(tol_resid=1e-6, n_max=8, max_iter=600, want_vector=False)
+        ref = None
+        if not args.no_davidson_ref:
+            ref, _ = ctx.davidson(tol_resid=1e-6, n_max=8, max_iter=600, want_vector=False)
         d64, _ = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600, want_vector=False)
         # the FP32 phase runs to half the target residual; FP64 sigma builds
         # then certify (and if needed finish) the solve
         dmx, _ = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600, precision=T.TBSCI_MIXED,
                               fp32_switch_resid=5e-5, want_vector=False)
+        e_ref = ref["energy"] if ref else None
+
+        def err(e):
+            return abs(e - e_ref) if ref else None
+
         result["davidson"] = {
             "stop": "FP64 residual norm <= 1e-4 (energy error ~ |r|^2/gap)",
-            "e_ref": ref["energy"], "ref_resid": ref["resid_norm"], "ref_iters": ref["iters"],
+            "e_ref": e_ref, "ref_resid": ref["resid_norm"] if ref else None,
+            "ref_iters": ref["iters"] if ref else None,
             "fp64": dict(time_s=d64["t_total_s"], sigma_s=d64["t_sigma_s"], iters=d64["iters"],
-                         energy=d64["energy"], abs_err=abs(d64["energy"] - ref["energy"]),
-                         converged=d64["converged"]),
+                         energy=d64["energy"], abs_err=err(d64["energy"]),
+                         resid=d64["resid_norm"], converged=d64["converged"]),
             "mixed": dict(time_s=dmx["t_total_s"], sigma_s=dmx["t_sigma_s"], iters=dmx["iters"],
                           iters_fp32=dmx["iters_fp32"], iters_fp64=dmx["iters_fp64"],
-                          energy=dmx["energy"], abs_err=abs(dmx["energy"] - ref["energy"]),
+                          energy=dmx["energy"], abs_err=err(dmx["energy"]),
                           abs_diff_vs_fp64=abs(dmx["energy"] - d64["energy"]),
-                          converged=dmx["converged"]),
+                          resid=dmx["resid_norm"], converged=dmx["converged"]),
             "speedup_mixed_vs_fp64": d64["t_total_s"] / dmx["t_total_s"],
         }
         print(f"# davidson fp64 {d64['t_total_s']:.3f}s ({d64['iters']} it), mixed "
               f"{dmx['t_total_s']:.3f}s ({dmx['iters_fp32']}+{dmx['iters_fp64']} it), "
-              f"E={ref['energy']:.10f}", file=sys.stderr, flush=True)
+              f"E64={d64['energy']:.10f} Emixed={dmx['energy']:.10f}", file=sys.stderr,
+              flush=True)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

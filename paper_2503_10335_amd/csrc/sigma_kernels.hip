@@ -17,6 +17,8 @@
 //                   alpha single excitations, multiply by the folded (pq|rs)
 //                   block on MFMA, scatter through the beta single lists
 //                   into the output row (LDS atomics when it fits in LDS);
+//                   the slab kernel when the integral fragments and the row
+//                   fit in LDS together, else the tile kernel;
 //   alpha sweep   : sparse rows of A_a times rows of C, one XCD per column
 //                   panel so each XCD's L2 holds its panel of C;
 //   beta sweep    : the same kernel on C^T, then a transpose-add.
@@ -505,6 +507,161 @@ __global__ __launch_bounds__(BOUND) void g_ab_tile(const AbDesc *__restrict__ d,
                             e.sb_grp, e.sb_off, (const T *)e.V, (const T *)e.C, (T *)e.S);
 }
 
+// Slab kernel: one output row I per block, waves independent of each other.
+// The A fragments of every M-tile (the signed integral rows U of the alpha
+// links of I) are staged in LDS once per row.  A wave takes 16-column slabs
+// of beta strings off a counter in LDS; per slab it loads its B fragments
+// (C[J_k][16 columns], the X of the tile kernel) straight from global
+// memory into registers and runs the M-tiles one after another: MFMA over
+// the links, then the scatter of the tile's accumulators through the beta
+// single lists into the FP64 row in LDS.  There is no barrier between
+// slabs, so one wave's MFMAs overlap other waves' loads and LDS atomics;
+// each C element is loaded once per row, by the wave that owns its slab.
+// LDS holds the whole FP64 row plus ceil(P/16) x ceil(K_max/4) fragments.
+struct SlabLds {
+    size_t row, a, aj, ctr, total;
+};
+
+inline SlabLds slab_lds(int64_t lb, int nmt, int nks, size_t sz) {
+    SlabLds L{};
+    size_t o = 0;
+    auto take = [&](size_t n) {
+        const size_t at = o;
+        o += (n + 15) & ~size_t(15);
+        return at;
+    };
+    L.row = take((size_t)lb * 8);
+    L.a = take((size_t)nmt * nks * 64 * sz);
+    L.aj = take((size_t)nks * 4 * 4);
+    L.ctr = take(4);
+    L.total = o;
+    return L;
+}
+
+template <typename T, int KS>
+__device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, int nmt,
+                                            const SlabLds L, const int64_t *__restrict__ sa_ptr,
+                                            const Ent *__restrict__ sa_ent,
+                                            const int64_t *__restrict__ sb_ptr,
+                                            const Ent *__restrict__ sb_grp,
+                                            const int32_t *__restrict__ sb_off,
+                                            const T *__restrict__ V, const T *__restrict__ C,
+                                            T *__restrict__ S) {
+    using M = Mfma<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *row = (double *)(smem + L.row);
+    T *afr = (T *)(smem + L.a);
+    int32_t *aj = (int32_t *)(smem + L.aj);
+    int *ctr = (int *)(smem + L.ctr);
+
+    const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const int g = lane >> 4, cl = lane & 15;
+    const int64_t a0 = sa_ptr[I];
+    const int K = (int)(sa_ptr[I + 1] - a0);
+    const int nks = (K + 3) >> 2;
+    const int ng = 4 * nmt;
+
+    for (int64_t i = tid; i < lb; i += nthr) row[i] = 0.0;
+    for (int k = tid; k < 4 * nks; k += nthr) aj[k] = k < K ? sa_ent[a0 + k].j : -1;
+    // A fragment (m, ks), lane ln: U[k = 4 ks + ln/16][pair of row ln%16 of tile m]
+    const int na = nmt * nks * 64;
+    for (int i = tid; i < na; i += nthr) {
+        const int ln = i & 63, q = i >> 6;
+        const int m = q / nks, ks = q - m * nks;
+        const int k = 4 * ks + (ln >> 4);
+        const int pr = 16 * m + a_row_pair<T>(ln & 15);
+        T a = T(0);
+        if (k < K && pr < P) {
+            const Ent e = sa_ent[a0 + k];
+            const T v = V[(int64_t)(e.o >> 16) * P + pr];
+            a = ((e.o >> 12) & 1u) ? -v : v;
+        }
+        afr[i] = a;
+    }
+    if (tid == 0) *ctr = 0;
+    __syncthreads();
+
+    const int64_t nslab = (lb + 15) >> 4;
+    for (;;) {
+        int sl = 0;
+        if (lane == 0) sl = atomicAdd(ctr, 1);
+        sl = __builtin_amdgcn_readfirstlane(sl);
+        if (sl >= nslab) break;
+        const int64_t col = (int64_t)sl * 16 + cl;
+        const bool cin = col < lb;
+        T b[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            T v = T(0);
+            if (ks < nks) {
+                const int32_t J = aj[4 * ks + g];
+                if (J >= 0 && cin) v = C[(int64_t)J * lb + col];
+            }
+            b[ks] = v;
+        }
+        const int32_t *off = sb_off + (cin ? col : 0) * (ng + 1) + g;
+        const int64_t base = cin ? sb_ptr[col] : 0;
+        for (int m = 0; m < nmt; ++m) {
+            typename M::acc_t acc = typename M::acc_t{0, 0, 0, 0};
+            const T *am = afr + (size_t)m * nks * 64 + lane;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                if (ks < nks) acc = M::mma(am[ks * 64], b[ks], acc);
+            int32_t o0 = 0, o1 = 0;
+            if (cin) {
+                o0 = off[4 * m];
+                o1 = off[4 * m + 1];
+            }
+            // register r holds pair 16 m + 4 r + g of this lane's column
+            for (int32_t x = o0; x < o1; ++x) {
+                const Ent e = sb_grp[base + x];
+                T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
+                if ((e.o >> 12) & 1u) v = -v;
+                atomicAdd(&row[e.j], (double)v);
+            }
+        }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < lb; i += nthr) S[I * lb + i] = (T)((double)S[I * lb + i] + row[i]);
+}
+
+constexpr int kSlabBlock = 1024;
+
+template <typename T, int KS>
+__global__ __launch_bounds__(kSlabBlock) void k_ab_slab(int64_t lb, int P, int nmt, SlabLds L,
+                                                       const int64_t *__restrict__ sa_ptr,
+                                                       const Ent *__restrict__ sa_ent,
+                                                       const int64_t *__restrict__ sb_ptr,
+                                                       const Ent *__restrict__ sb_grp,
+                                                       const int32_t *__restrict__ sb_off,
+                                                       const T *__restrict__ V,
+                                                       const T *__restrict__ C,
+                                                       T *__restrict__ S) {
+    ab_slab_row<T, KS>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off, V, C,
+                       S);
+}
+
+// one problem of a grouped slab launch: blocks [blk0, blk0 + l_alpha)
+struct SlabDesc {
+    int64_t blk0, lb;
+    SlabLds L;
+    const int64_t *sa_ptr;
+    const Ent *sa_ent;
+    const int64_t *sb_ptr;
+    const Ent *sb_grp;
+    const int32_t *sb_off;
+    const void *V, *C;
+    void *S;
+};
+
+template <typename T, int KS>
+__global__ __launch_bounds__(kSlabBlock) void g_ab_slab(const SlabDesc *__restrict__ d, int nd,
+                                                       int P, int nmt) {
+    const SlabDesc e = d[find_desc(d, nd, blockIdx.x)];
+    ab_slab_row<T, KS>(blockIdx.x - e.blk0, e.lb, P, nmt, e.L, e.sa_ptr, e.sa_ent, e.sb_ptr,
+                       e.sb_grp, e.sb_off, (const T *)e.V, (const T *)e.C, (T *)e.S);
+}
+
 // ---------------------------------------------------------------- driver
 
 template <typename T>
@@ -592,9 +749,38 @@ void launch_ab_ks(Ctx &c, const T *C, T *S, hipStream_t st) {
         launch_ab_kb<T, KS, 1024>(c, C, S, st);
 }
 
+// KS instance of the slab kernel for a context (0: it does not apply)
+int slab_ks(const Ctx &c, size_t sz) {
+    const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
+    if (ks > 24) return 0;
+    if (slab_lds(c.sp[1].l, (c.P + 15) / 16, ks, sz).total > kLdsMax) return 0;
+    return (ks + 3) / 4 * 4;
+}
+
+template <typename T, int KS>
+void launch_ab_slab(Ctx &c, const T *C, T *S, hipStream_t st) {
+    const Spin &A = c.sp[0], &B = c.sp[1];
+    const int P = c.P, nmt = (P + 15) / 16;
+    const SlabLds L = slab_lds(B.l, nmt, std::max((A.max_s + 3) / 4, 1), sizeof(T));
+    auto f = k_ab_slab<T, KS>;
+    if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
+    f<<<(unsigned)A.l, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
+                                                  B.g_ent, B.g_off, Vals<T>::V(c), C, S);
+    TB_HIP(hipGetLastError());
+}
+
 // opposite-spin term; returns false if this shape needs the direct kernel
 template <typename T>
 bool launch_ab(Ctx &c, const T *C, T *S, hipStream_t st) {
+    switch (slab_ks(c, sizeof(T))) {
+        case 4: launch_ab_slab<T, 4>(c, C, S, st); return true;
+        case 8: launch_ab_slab<T, 8>(c, C, S, st); return true;
+        case 12: launch_ab_slab<T, 12>(c, C, S, st); return true;
+        case 16: launch_ab_slab<T, 16>(c, C, S, st); return true;
+        case 20: launch_ab_slab<T, 20>(c, C, S, st); return true;
+        case 24: launch_ab_slab<T, 24>(c, C, S, st); return true;
+        default: break;
+    }
     const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
     const int nmt = (c.P + 15) / 16;
     if (ks > 32 || nmt > 16) return false;
@@ -709,6 +895,23 @@ void launch_ab_group(const AbDesc *dd, int nd, int64_t blocks, int P, int KS, si
 }
 
 template <typename T>
+void launch_slab_group(const SlabDesc *dd, int nd, int64_t blocks, int P, int KS, size_t lds,
+                       Ctx &c0, hipStream_t st) {
+    const int nmt = (P + 15) / 16;
+    auto f = KS == 4    ? g_ab_slab<T, 4>
+             : KS == 8  ? g_ab_slab<T, 8>
+             : KS == 12 ? g_ab_slab<T, 12>
+             : KS == 16 ? g_ab_slab<T, 16>
+             : KS == 20 ? g_ab_slab<T, 20>
+             : KS == 24 ? g_ab_slab<T, 24>
+                        : nullptr;
+    if (!f) throw Error(TBSCI_E_DEVICE, "no grouped slab kernel for this shape");
+    if (lds > 64 * 1024) allow_lds(c0, (const void *)f, lds);
+    f<<<(unsigned)blocks, kSlabBlock, lds, st>>>(dd, nd, P, nmt);
+    TB_HIP(hipGetLastError());
+}
+
+template <typename T>
 void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, TableArena &ar,
                       hipStream_t st) {
     std::vector<SweepDesc> sa, sb;
@@ -737,6 +940,13 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
         std::vector<AbDesc> d;
     };
     std::vector<Group> groups;
+    struct SlabGroup {
+        int P, KS;
+        size_t lds;
+        int64_t blocks;
+        std::vector<SlabDesc> d;
+    };
+    std::vector<SlabGroup> sgroups;
     std::vector<int> direct;
     for (int i = 0; i < n; ++i) {
         Ctx &c = *ctx[i];
@@ -746,6 +956,23 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
         trans(t1, bt1, A.l, B.l, C[i], Ct);
         sweep(sb, bsb, B, A.l, Ct, St);
         trans(t2, bt2, B.l, A.l, St, S[i]);
+        const int SK = slab_ks(c, sizeof(T));
+        if (SK) {  // slab kernel; problems with the same P and KS share a launch
+            const SlabLds L =
+                slab_lds(B.l, (c.P + 15) / 16, std::max((A.max_s + 3) / 4, 1), sizeof(T));
+            SlabGroup *g = nullptr;
+            for (auto &x : sgroups)
+                if (x.P == c.P && x.KS == SK) g = &x;
+            if (!g) {
+                sgroups.push_back(SlabGroup{c.P, SK, 0, 0, {}});
+                g = &sgroups.back();
+            }
+            g->d.push_back(SlabDesc{g->blocks, B.l, L, A.s_ptr, A.s_ent, B.s_ptr, B.g_ent,
+                                    B.g_off, Vals<T>::V(c), C[i], S[i]});
+            g->blocks += A.l;
+            g->lds = std::max(g->lds, L.total);
+            continue;
+        }
         const int KS = ab_ks(c);
         const AbLds L = ab_lds(B.l, 4 * std::max(KS, 1), sizeof(T), 8);
         if (KS == 0 || L.nrow < B.l) {  // grouped kernels hold whole FP64 rows
@@ -771,12 +998,17 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
     const TransDesc *dt2 = ar.stage(t2.data(), t2.size());
     std::vector<const AbDesc *> dg;
     for (auto &g : groups) dg.push_back(ar.stage(g.d.data(), g.d.size()));
+    std::vector<const SlabDesc *> dsg;
+    for (auto &g : sgroups) dsg.push_back(ar.stage(g.d.data(), g.d.size()));
     ar.flush(st);
     g_row_sweep<T, false><<<(unsigned)bsa, kBlock, 0, st>>>(dsa, n);  // sigma = A_a C
     g_transpose<T, false><<<(unsigned)bt1, kBlock, 0, st>>>(dt1, n);
     g_row_sweep<T, false><<<(unsigned)bsb, kBlock, 0, st>>>(dsb, n);
     g_transpose<T, true><<<(unsigned)bt2, kBlock, 0, st>>>(dt2, n);  // sigma += (A_b C^T)^T
     TB_HIP(hipGetLastError());
+    for (size_t k = 0; k < sgroups.size(); ++k)
+        launch_slab_group<T>(dsg[k], (int)sgroups[k].d.size(), sgroups[k].blocks, sgroups[k].P,
+                             sgroups[k].KS, sgroups[k].lds, *ctx[0], st);
     for (size_t k = 0; k < groups.size(); ++k)
         launch_ab_group<T>(dg[k], (int)groups[k].d.size(), groups[k].blocks, groups[k].P,
                            groups[k].KS, groups[k].lds, *ctx[0], st);
@@ -843,14 +1075,15 @@ double executed_flops(Ctx &c, int kernel, int precision) {
     if (kernel == 1) return 2.0 * (double)B.n_a * (double)A.l;
     const int ks = std::max((A.max_s + 3) / 4, 1);
     const int nmt = (c.P + 15) / 16;
-    (void)precision;
+    const bool slab = slab_ks(c, precision == TBSCI_FP32 ? sizeof(float) : sizeof(double)) > 0;
     const bool tile = ks <= 32 && nmt <= 16 && 4 * ks * kTW <= kXPT * 64 * nmt;
-    if (!tile) return 2.0 * (double)A.n_s * (double)B.n_s;
+    if (!slab && !tile) return 2.0 * (double)A.n_s * (double)B.n_s;
     std::vector<int64_t> ptr((size_t)A.l + 1);
     TB_HIP(hipMemcpy(ptr.data(), A.s_ptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
     double kp = 0.0;
     for (int64_t i = 0; i < A.l; ++i) kp += (double)(4 * ((ptr[i + 1] - ptr[i] + 3) / 4));
-    const double cols = (double)((B.l + kTW - 1) / kTW) * kTW;
+    const int w = slab ? 16 : kTW;  // columns per MFMA pass: slab or tile
+    const double cols = (double)((B.l + w - 1) / w) * w;
     return 2.0 * kp * (16.0 * nmt) * cols;
 }
 

@@ -530,9 +530,10 @@ inline SlabLds slab_lds(int64_t lb, int nmt, int nks, size_t sz) {
         o += (n + 15) & ~size_t(15);
         return at;
     };
+    const int nk4 = (nks + 3) / 4 * 4;  // k-steps padded to the largest chunk
     L.row = take((size_t)lb * 8);
-    L.a = take((size_t)nmt * nks * 64 * sz);
-    L.aj = take((size_t)nks * 4 * 4);
+    L.a = take((size_t)nmt * nk4 * 64 * sz);
+    L.aj = take((size_t)nk4 * 4 * 4);
     L.ctr = take(4);
     L.total = o;
     return L;
@@ -558,7 +559,12 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
     const int g = lane >> 4, cl = lane & 15;
     const int64_t a0 = sa_ptr[I];
     const int K = (int)(sa_ptr[I + 1] - a0);
-    const int nks = (K + 3) >> 2;
+    // k-steps of 4 links, run in chunks of CK MFMAs (padding steps hold
+    // zero fragments); FP32 takes chunks of 4 with the C loads of a chunk
+    // issued together, FP64 single steps (its MFMA time dominates, padding
+    // would add to it)
+    constexpr int CK = sizeof(T) == 8 ? 1 : 4;
+    const int nks = (((K + 3) >> 2) + CK - 1) / CK * CK;
     const int ng = 4 * nmt;
 
     for (int64_t i = tid; i < lb; i += nthr) row[i] = 0.0;
@@ -590,35 +596,73 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
         const int64_t col = (int64_t)sl * 16 + cl;
         const bool cin = col < lb;
         T b[KS];
+        if constexpr (CK == 1) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            T v = T(0);
-            if (ks < nks) {
-                const int32_t J = aj[4 * ks + g];
-                if (J >= 0 && cin) v = C[(int64_t)J * lb + col];
+            for (int ks = 0; ks < KS; ++ks) {
+                T v = T(0);
+                if (ks < nks) {
+                    const int32_t J = aj[4 * ks + g];
+                    if (J >= 0 && cin) v = C[(int64_t)J * lb + col];
+                }
+                b[ks] = v;
             }
-            b[ks] = v;
+        } else {
+#pragma unroll
+            for (int q = 0; q < KS / CK; ++q)
+                if (CK * q < nks) {
+                    int32_t J[CK];
+#pragma unroll
+                    for (int u = 0; u < CK; ++u) J[u] = aj[4 * (CK * q + u) + g];
+#pragma unroll
+                    for (int u = 0; u < CK; ++u) {  // in-bounds load, then select
+                        const bool ok = J[u] >= 0 && cin;
+                        const T v = C[ok ? (int64_t)J[u] * lb + col : 0];
+                        b[CK * q + u] = ok ? v : T(0);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < CK; ++u) b[CK * q + u] = T(0);
+                }
         }
         const int32_t *off = sb_off + (cin ? col : 0) * (ng + 1) + g;
         const int64_t base = cin ? sb_ptr[col] : 0;
+        int32_t n0 = 0, n1 = 0;  // link range of the next tile
+        if (cin) {
+            n0 = off[0];
+            n1 = off[1];
+        }
         for (int m = 0; m < nmt; ++m) {
+            const int32_t o0 = n0, o1 = n1;
+            // the first two links of this tile and the next tile's range are
+            // loaded before the MFMAs, so they arrive while those run
+            Ent e0{0, 0}, e1{0, 0};
+            const bool h0 = o0 < o1, h1 = o0 + 1 < o1;
+            if (h0) e0 = sb_grp[base + o0];
+            if (h1) e1 = sb_grp[base + o0 + 1];
+            if (cin && m + 1 < nmt) {
+                n0 = off[4 * (m + 1)];
+                n1 = off[4 * (m + 1) + 1];
+            }
             typename M::acc_t acc = typename M::acc_t{0, 0, 0, 0};
             const T *am = afr + (size_t)m * nks * 64 + lane;
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                if (ks < nks) acc = M::mma(am[ks * 64], b[ks], acc);
-            int32_t o0 = 0, o1 = 0;
-            if (cin) {
-                o0 = off[4 * m];
-                o1 = off[4 * m + 1];
-            }
+            for (int q = 0; q < KS / CK; ++q)
+                if (CK * q < nks) {
+                    T a[CK];
+#pragma unroll
+                    for (int u = 0; u < CK; ++u) a[u] = am[(CK * q + u) * 64];
+#pragma unroll
+                    for (int u = 0; u < CK; ++u) acc = M::mma(a[u], b[CK * q + u], acc);
+                }
             // register r holds pair 16 m + 4 r + g of this lane's column
-            for (int32_t x = o0; x < o1; ++x) {
-                const Ent e = sb_grp[base + x];
+            auto put = [&](const Ent &e) {
                 T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
                 if ((e.o >> 12) & 1u) v = -v;
                 atomicAdd(&row[e.j], (double)v);
-            }
+            };
+            if (h0) put(e0);
+            if (h1) put(e1);
+            for (int32_t x = o0 + 2; x < o1; ++x) put(sb_grp[base + x]);
         }
     }
     __syncthreads();

@@ -270,3 +270,59 @@ def test_sigma_chunked_sweeps(env, shape):
     got32 = ctx.sigma(Cg.float(), precision=T.TBSCI_FP32).double().cpu().numpy()
     assert _rel(got32, ref)[0] <= 2e-5
     ctx.close()
+
+
+def _shell_alpha(M, N):
+    """The lowest string (orbitals 0..N-1) and all of its single excitations."""
+    ref = (1 << N) - 1
+    out = [ref] + [ref ^ (1 << i) ^ (1 << a) for i in range(N) for a in range(N, M)]
+    return np.array(out, dtype=np.uint64)
+
+
+def test_sigma_tile_kernel_many_links(env):
+    """An alpha string with more alpha links than the slab kernel takes (the
+    reference string of a single-excitation shell at M = 20 has 100 singles
+    plus 10 occupations): the opposite-spin term runs in the tile kernel,
+    whole FP64 row in LDS.  FP64 and FP32 sigma against the oracle."""
+    T, O, torch = env
+    M, N = 20, 10
+    h, eri = W.integrals(M, 41)
+    rng = np.random.default_rng(42)
+    B = W.all_strings(M, N)
+    beta = np.ascontiguousarray(B[rng.permutation(len(B))[:60]])
+    p = W.Problem("shell_m20", M, N, N, h, eri, _shell_alpha(M, N), beta)
+    ptr, _ = O.lists(p.alpha, M, 1)
+    assert int(np.diff(ptr).max()) + N == 110
+    ctx = T.Context.from_problem(p)
+    C = np.random.default_rng(5).normal(size=(len(p.alpha), len(p.beta)))
+    ref = O.Space.of(p).sigma(C, nthreads=16)
+    Cg = torch.from_numpy(C).cuda()
+    e, m = _rel(ctx.sigma(Cg).cpu().numpy(), ref)
+    assert e <= 1e-12 and m <= 1e-12
+    got32 = ctx.sigma(Cg.float(), precision=T.TBSCI_FP32).double().cpu().numpy()
+    assert _rel(got32, ref)[0] <= 2e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(24, 18000), (16, 21000)])
+def test_sigma_tile_kernel_long_rows(env, shape):
+    """Beta lists too long for the slab kernel's LDS (an FP64 row of 18000 or
+    21000 strings plus FP64 fragments): FP64 sigma in the tile kernel, with
+    the whole FP64 row in LDS (18000) or the row split between LDS and
+    global atomics (21000).  FP32 sigma: the slab kernel (18000; its
+    fragments are half the size) or the tile kernel with a whole FP32 row
+    in LDS (21000).  Eight alpha rows, first and last included, against the
+    oracle."""
+    T, O, torch = env
+    la, lb = shape
+    p = W.random_selection(18, 9, 9, la, lb, seed=43)
+    ctx = T.Context.from_problem(p)
+    C = np.random.default_rng(6).normal(size=(la, lb))
+    rows = np.unique(np.r_[0, la - 1, np.random.default_rng(7).choice(la, 6, replace=False)])
+    ref = O.Space.of(p).sigma(C, rows=rows, nthreads=16)
+    Cg = torch.from_numpy(C).cuda()
+    e, m = _rel(ctx.sigma(Cg).cpu().numpy()[rows], ref)
+    assert e <= 1e-12 and m <= 1e-12
+    got32 = ctx.sigma(Cg.float(), precision=T.TBSCI_FP32).double().cpu().numpy()[rows]
+    assert _rel(got32, ref)[0] <= 2e-5
+    ctx.close()

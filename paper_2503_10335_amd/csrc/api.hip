@@ -155,7 +155,8 @@ size_t spin_bytes(int M, int P, int n, int64_t l, int64_t n_s, int64_t n_d) {
     const size_t L = (size_t)l;
     const int64_t n_a = l + (n_s - (int64_t)n * l) + n_d;
     const size_t ngroup = 4 * (size_t)((P + 15) / 16);
-    const size_t nch = (size_t)((l + kSweepChunk - 1) / kSweepChunk);
+    const int64_t chunk = sweep_chunk(l, n_a);
+    const size_t nch = chunk ? (size_t)((l + chunk - 1) / chunk) : 1;
     const size_t chunked = nch > 1 ? page(4 * L * (nch + 1)) + page(4 * (size_t)n_a) +
                                          page(8 * (size_t)n_a) + page(4 * (size_t)n_a)
                                    : 0;

@@ -452,14 +452,15 @@ void build_spin(Ctx &c, Spin &s, const uint64_t *host_str, hipStream_t st) {
     k_same_spin<<<wblocks, kBlock, 0, st>>>(s.str, l, M, c.h, c.eri, s.s_ptr, s.s_ent, s.d_ptr,
                                              s.d_ent, s.dsame, s.a_ptr, s.a_col, s.a_val, s.a_val32);
     TB_HIP(hipGetLastError());
-    s.nch = (int)((l + kSweepChunk - 1) / kSweepChunk);
+    s.chunk = sweep_chunk(l, s.n_a);
+    s.nch = s.chunk ? (int)((l + s.chunk - 1) / s.chunk) : 1;
     if (s.nch > 1) {
         s.b_off = dalloc<int32_t>((size_t)l * (s.nch + 1));
         s.b_col = dalloc<int32_t>(s.n_a);
         s.b_val = dalloc<double>(s.n_a);
         s.b_val32 = dalloc<float>(s.n_a);
         k_chunk_rows<<<blocks_for(l, 128), 128, 0, st>>>(s.a_ptr, s.a_col, s.a_val, s.a_val32, l,
-                                                          s.nch, kSweepChunk, s.b_off, s.b_col,
+                                                          s.nch, s.chunk, s.b_off, s.b_col,
                                                           s.b_val, s.b_val32);
         TB_HIP(hipGetLastError());
     }

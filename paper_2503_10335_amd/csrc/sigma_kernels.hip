@@ -145,6 +145,96 @@ __global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t nco
                                X, Y, chk, nch, ch);
 }
 
+// Panel sweep: Y (+)= A_s X for one column tile (64 V columns) and a block
+// of kPanelBlockRows output rows.  The tile of X is staged in LDS one panel
+// of kPanelRows source rows at a time, and each wave accumulates its 4
+// output rows from their entries in that panel (the source-chunked CSR), so
+// the gathers read LDS instead of L2.  Tiles are dealt to XCDs round-robin,
+// so the blocks of one tile stage the same panels out of their XCD's L2.
+constexpr int kPanelBlockRows = 64;
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelRowsPerWave = kPanelBlockRows / (kPanelThreads / 64);
+
+template <typename T, bool ACC, int V>
+__global__ __launch_bounds__(kPanelThreads) void k_panel_sweep(
+    int64_t nrows, int64_t ncols, int64_t ntiles, int64_t nrb, int64_t tiles_per_xcd,
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ off, int npc,
+    const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ X,
+    T *__restrict__ Y) {
+    using TV = typename Vec<T, V>::type;
+    constexpr int RW = kPanelRowsPerWave;
+    __shared__ TV xs[kPanelRows * 64];
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b % kXcd, local = b / kXcd;
+    const int64_t tl = local / nrb, rb = local - tl * nrb;
+    const int64_t tile = xcd + kXcd * tl;
+    if (tl >= tiles_per_xcd || tile >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t ld = ncols / V;  // row length of X and Y in TV units
+    const TV *__restrict__ Xt = (const TV *)X + tile * 64;
+    const int64_t I0 = rb * kPanelBlockRows + wave * RW;
+    int64_t base[RW];
+    const int32_t *ro[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const bool v = I0 + r < nrows;
+        base[r] = v ? ptr[I0 + r] : 0;
+        ro[r] = off + (v ? I0 + r : 0) * (npc + 1);
+    }
+    TV acc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r] = Vec<T, V>::zero();
+    for (int ch = 0; ch < npc; ++ch) {
+        const int64_t j0 = (int64_t)ch * kPanelRows;
+        // stage source rows j0 .. j0 + kPanelRows - 1 of the tile
+#pragma unroll
+        for (int k = 0; k < kPanelRows * 64 / kPanelThreads; ++k) {
+            const int i = tid + k * kPanelThreads;
+            const int64_t jr = j0 + (i >> 6);
+            const int ln = i & 63;
+            TV x = Vec<T, V>::zero();
+            if (jr < nrows && tile * 64 + ln < ld) x = Xt[jr * ld + ln];
+            xs[i] = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            if (I0 + r >= nrows) break;
+            int64_t e = base[r] + ro[r][ch];
+            const int64_t e1 = base[r] + ro[r][ch + 1];
+            for (; e + 4 <= e1; e += 4) {
+                int32_t j[4];
+                T v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    j[u] = col[e + u] - (int32_t)j0;
+                    v[u] = val[e + u];
+                }
+                TV x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = xs[j[u] * 64 + lane];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[r] += v[u] * x[u];
+            }
+            for (; e < e1; ++e) acc[r] += val[e] * xs[(col[e] - (int32_t)j0) * 64 + lane];
+        }
+        __syncthreads();
+    }
+    const int64_t cl = tile * 64 + lane;  // this lane's column in TV units
+    if (cl < ld) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            if (I0 + r >= nrows) break;
+            TV *y = (TV *)Y + (I0 + r) * ld + cl;
+            if (ACC)
+                *y += acc[r];
+            else
+                *y = acc[r];
+        }
+    }
+}
+
 // Descriptor of one problem in a grouped launch; the problem's blocks are
 // [blk0, blk0 + its block count), blk0 a multiple of 8 so that the XCD of a
 // block is the same as in a launch of its own.
@@ -729,11 +819,26 @@ template <typename T>
 void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st) {
     const int64_t nrows = s.l;
     const int vec = sweep_vec(ncols);
+    // FP64: one launch, panels staged in LDS (FP32 gathers half the bytes
+    // per entry and measured faster with the plain sweep out of L2)
+    if (s.chunk == kPanelRows && sizeof(T) == 8) {
+        const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec);
+        const int64_t nrb = (nrows + kPanelBlockRows - 1) / kPanelBlockRows;
+        const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
+        const unsigned grid = (unsigned)(kXcd * tpx * nrb);
+        auto f = vec == 2 ? (acc ? k_panel_sweep<T, true, 2> : k_panel_sweep<T, false, 2>)
+                          : (acc ? k_panel_sweep<T, true, 1> : k_panel_sweep<T, false, 1>);
+        f<<<grid, kPanelThreads, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr, s.b_off,
+                                          s.nch, s.b_col, Vals<T>::b(s), X, Y);
+        TB_HIP(hipGetLastError());
+        return;
+    }
     const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec), nrb = (nrows + 3) / 4;
     const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
     const unsigned grid = (unsigned)(kXcd * tpx * nrb);
-    const bool chunked = s.nch > 1;
-    for (int ch = 0; ch < s.nch; ++ch) {
+    const bool chunked = s.chunk == kSweepChunk && s.nch > 1;
+    const int nch = chunked ? s.nch : 1;
+    for (int ch = 0; ch < nch; ++ch) {
         const bool a = acc || ch > 0;
         auto f = vec == 2 ? (a ? k_row_sweep<T, true, 2> : k_row_sweep<T, false, 2>)
                           : (a ? k_row_sweep<T, true, 1> : k_row_sweep<T, false, 1>);

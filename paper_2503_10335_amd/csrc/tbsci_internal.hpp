@@ -57,9 +57,10 @@ struct Spin {
     int32_t *a_col = nullptr;
     double *a_val = nullptr;
     float *a_val32 = nullptr;
-    // the same rows grouped by source chunk (chunks of kSweepChunk strings)
-    // for the L2-blocked sweep, when there is more than one chunk:
+    // the same rows grouped by source chunk of `chunk` strings (see
+    // sweep_chunk), when there is more than one chunk:
     // row I's entries with col in chunk c are b_*[a_ptr[I] + b_off[I (nch + 1) + c] ...]
+    int64_t chunk = 0;
     int nch = 1;
     int32_t *b_off = nullptr;
     int32_t *b_col = nullptr;
@@ -79,6 +80,19 @@ struct Spin {
 // Sweep source chunk: the gathered rows of one chunk, 128 columns wide in
 // FP64, fill 3 MB of an XCD's 4 MB L2
 constexpr int64_t kSweepChunk = 3072;
+// Panel sweep: source rows staged in LDS this many at a time
+constexpr int64_t kPanelRows = 64;
+
+// Source chunk of a spin's same-spin rows for the sweeps: kPanelRows (LDS
+// panels) when the spin has at most kSweepChunk strings and its rows hold
+// at least 4 entries per panel on average; kSweepChunk (one L2-resident
+// pass per chunk) for more strings; 0 for a single plain pass.
+inline int64_t sweep_chunk(int64_t l, int64_t n_a) {
+    if (l > kSweepChunk) return kSweepChunk;
+    const int64_t npc = (l + kPanelRows - 1) / kPanelRows;
+    if (npc > 1 && n_a >= 4 * npc * l) return kPanelRows;
+    return 0;
+}
 
 struct Ctx {
     int M = 0, P = 0, device = 0;

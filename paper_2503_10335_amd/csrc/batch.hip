@@ -1024,18 +1024,19 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     bool handover = false;
     if (s.fp32) {
         // The FP32 phase ends at fp32_switch_resid, or when the residual
-        // has stopped improving close to the FP32 rounding floor of the
-        // sigma build (taken as 2e-6 |theta|), or when no new direction is
-        // left; a plateau well above that floor is slow convergence, which
-        // FP64 would not cure.
+        // has stopped improving for 30 iterations within 2x of the FP32
+        // rounding floor of the sigma build (taken as 2e-6 |theta|), or at
+        // half the iteration budget, or when no new direction is left.  A
+        // plateau above that is slow convergence, which FP64 would not cure
+        // (FP64 solves of the same problems show plateaus of 40 iterations).
         if (s.rn < 0.98 * s.best_rn) {
             s.best_rn = s.rn;
             s.since_best = 0;
         } else {
             ++s.since_best;
         }
-        const bool at_floor = s.rn < 10.0 * 2e-6 * std::fabs(s.theta);
-        handover = s.rn <= s.o.fp32_switch_resid || (s.since_best >= 20 && at_floor) ||
+        const bool at_floor = s.rn < 2.0 * 2e-6 * std::fabs(s.theta);
+        handover = s.rn <= s.o.fp32_switch_resid || (s.since_best >= 30 && at_floor) ||
                    s.info.iters >= s.o.max_iter / 2 || dropped;
     } else if (s.rn <= s.o.tol_resid &&
                (s.o.tol_energy <= 0.0 || std::fabs(s.theta - s.theta_prev) <= s.o.tol_energy)) {

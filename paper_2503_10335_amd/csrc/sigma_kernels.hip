@@ -687,13 +687,14 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
         const bool cin = col < lb;
         T b[KS];
         if constexpr (CK == 1) {
+            // the link rows first (one LDS round trip), then the loads
+            int32_t J[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) J[ks] = ks < nks ? aj[4 * ks + g] : -1;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 T v = T(0);
-                if (ks < nks) {
-                    const int32_t J = aj[4 * ks + g];
-                    if (J >= 0 && cin) v = C[(int64_t)J * lb + col];
-                }
+                if (J[ks] >= 0 && cin) v = C[(int64_t)J[ks] * lb + col];
                 b[ks] = v;
             }
         } else {
@@ -723,12 +724,14 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
         }
         for (int m = 0; m < nmt; ++m) {
             const int32_t o0 = n0, o1 = n1;
-            // the first two links of this tile and the next tile's range are
+            // the first four links of this tile and the next tile's range are
             // loaded before the MFMAs, so they arrive while those run
-            Ent e0{0, 0}, e1{0, 0};
-            const bool h0 = o0 < o1, h1 = o0 + 1 < o1;
+            Ent e0{0, 0}, e1{0, 0}, e2{0, 0}, e3{0, 0};
+            const bool h0 = o0 < o1, h1 = o0 + 1 < o1, h2 = o0 + 2 < o1, h3 = o0 + 3 < o1;
             if (h0) e0 = sb_grp[base + o0];
             if (h1) e1 = sb_grp[base + o0 + 1];
+            if (h2) e2 = sb_grp[base + o0 + 2];
+            if (h3) e3 = sb_grp[base + o0 + 3];
             if (cin && m + 1 < nmt) {
                 n0 = off[4 * (m + 1)];
                 n1 = off[4 * (m + 1) + 1];
@@ -752,7 +755,9 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
             };
             if (h0) put(e0);
             if (h1) put(e1);
-            for (int32_t x = o0 + 2; x < o1; ++x) put(sb_grp[base + x]);
+            if (h2) put(e2);
+            if (h3) put(e3);
+            for (int32_t x = o0 + 4; x < o1; ++x) put(sb_grp[base + x]);
         }
     }
     __syncthreads();

@@ -450,6 +450,8 @@ def serving_leg(T, W, n_req, load):
     run([0.0])  # warm-up: first launches load code objects
     sat, sat_span, sat_st = run([0.0] * n_req)
     capacity = n_req / sat_span
+    print(f"# serving {n_req} requests at once: {sat_span:.2f}s, capacity {capacity:.2f}/s",
+          file=sys.stderr, flush=True)
     rate = load * capacity
     # unit-rate Poisson arrival times of the mix, rescaled to this rate
     arrivals = [r["t_arrive"] / rate for r in base]
@@ -461,11 +463,13 @@ def serving_leg(T, W, n_req, load):
     # sequential FP64 baseline, first come first served
     t1 = time.perf_counter()
     seq_e = []
-    for p in probs:
+    for i, p in enumerate(probs):
         c = T.Context.from_problem(p)
         info, _ = c.davidson(tol_resid=1e-4, n_max=8, max_iter=600, want_vector=False)
         seq_e.append(info["energy"])
         c.close()
+        if (i + 1) % 64 == 0:
+            print(f"# sequential fp64: {i + 1} of {n_req} solved", file=sys.stderr, flush=True)
     seq_s = time.perf_counter() - t1
     diff = max(abs(r["energy"] - e) for r, e in zip(res, seq_e))
     print(f"# sequential fp64 {seq_s:.2f}s ({n_req / seq_s:.2f}/s), max |E_serving - E_fp64| "

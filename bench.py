@@ -344,11 +344,17 @@ def main():
         ref = None
         if not args.no_davidson_ref:
             ref, _ = ctx.davidson(tol_resid=1e-6, n_max=8, max_iter=600, want_vector=False)
-        d64, _ = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600, want_vector=False)
+        # the eigenvectors go to host memory for the oracle check of the
+        # cpu_baseline leg
+        d64, X = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600)
+        eig_host = {"fp64": (d64["energy"], X.cpu().numpy())}
+        del X
         # the FP32 phase runs to half the target residual; FP64 sigma builds
         # then certify (and if needed finish) the solve
-        dmx, _ = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600, precision=T.TBSCI_MIXED,
-                              fp32_switch_resid=5e-5, want_vector=False)
+        dmx, X = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600, precision=T.TBSCI_MIXED,
+                              fp32_switch_resid=5e-5)
+        eig_host["mixed"] = (dmx["energy"], X.cpu().numpy())
+        del X
         e_ref = ref["energy"] if ref else None
 
         def err(e):
@@ -403,6 +409,22 @@ def main():
         }
         print(f"# cpu oracle {n_rows} rows in {tc:.1f}s on {threads} threads, parity {err:.2e}",
               file=sys.stderr, flush=True)
+        if "davidson" in result:
+            # the oracle's (H x)_K on 16 seeded alpha rows against E x_K: no
+            # component of H x - E x can exceed the solver's residual norm
+            srows = np.sort(rng.choice(ctx.l_alpha, size=min(16, ctx.l_alpha), replace=False))
+            need = sp.linked_rows(srows)
+            for leg, (energy, xh) in eig_host.items():
+                hx = sp.sigma_rows_from(srows, xh[need], need, nthreads=threads)
+                dev = float(np.abs(hx - energy * xh[srows]).max())
+                result["davidson"][leg]["sampled_residual"] = dev
+            result["davidson"]["oracle_check"] = (
+                f"sampled_residual = max_K |(H x)_K - E x_K|, (H x)_K from the oracle on "
+                f"{len(srows)} seeded alpha rows x {ctx.l_beta} beta columns; bounded by resid")
+            print(f"# oracle check of the eigenvectors: max |Hx - Ex| fp64 "
+                  f"{result['davidson']['fp64']['sampled_residual']:.2e}, mixed "
+                  f"{result['davidson']['mixed']['sampled_residual']:.2e}", file=sys.stderr,
+                  flush=True)
 
     ctx.close()
     if args.serving_requests > 0:

@@ -88,3 +88,33 @@ def test_fci_m18_fp64_fp32_sampled(env):
     assert np.all(np.diff(ptr) == 9 * 9 + 9)
     _check_rows(O, T, torch, p, ctx, np.array([0, 24310, 48619]), spin_flip=True)
     ctx.close()
+
+
+def test_selected_m16_davidson_sampled_residual(env):
+    """The full-size Davidson eigenpair against the oracle, with no oracle
+    solve: on 32 seeded alpha rows the oracle's (H x)_K must equal E x_K to
+    within the solver's residual norm (no component of H x - E x exceeds its
+    norm), for the FP64 solve and for the mixed one, whose energies agree to
+    1e-6 Eh."""
+    T, O, torch = env
+    p = W.config("sel_m16")
+    ctx = T.Context.from_problem(p)
+    sp = O.Space.of(p)
+    rows = np.sort(np.random.default_rng(21).choice(ctx.l_alpha, 32, replace=False))
+    need = sp.linked_rows(rows)
+    energies = []
+    for prec in (T.TBSCI_FP64, T.TBSCI_MIXED):
+        info, X = ctx.davidson(tol_resid=1e-6, n_max=8, max_iter=600, precision=prec)
+        assert info["status"] == T.TBSCI_OK and info["converged"]
+        assert info["resid_norm"] <= 1e-6
+        xs = X[torch.from_numpy(need).cuda()].cpu().numpy()
+        hx = sp.sigma_rows_from(rows, xs, need, nthreads=16)
+        ex = info["energy"] * X[torch.from_numpy(rows).cuda()].cpu().numpy()
+        dev = np.abs(hx - ex).max()
+        print(f"sel_m16 prec {prec}: E {info['energy']:.10f} |r| {info['resid_norm']:.2e} "
+              f"sampled max |Hx - Ex| {dev:.2e}", flush=True)
+        assert dev <= info["resid_norm"] + 1e-9
+        energies.append(info["energy"])
+        del X
+    assert abs(energies[0] - energies[1]) <= 1e-6
+    ctx.close()

@@ -67,10 +67,16 @@ struct Vec<T, 2> {
     typedef T type __attribute__((ext_vector_type(2)));
     static __device__ __forceinline__ type zero() { return type{T(0), T(0)}; }
 };
+template <typename T>
+struct Vec<T, 4> {
+    typedef T type __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ type zero() { return type{T(0), T(0), T(0), T(0)}; }
+};
 
-// V = columns per lane: 2 when ncols is even (one 16-byte load per lane per
-// nonzero in FP64, so rows start aligned), else 1; a wave covers 64 V
-// columns of its row
+// V = columns per lane, a divisor of ncols (so rows start aligned): 2 when
+// ncols is even (one 16-byte load per lane per nonzero in FP64), 4 for FP32
+// when ncols is a multiple of 4, else 1; a wave covers 64 V columns of its
+// row
 template <typename T, bool ACC, int V>
 __device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_t ncols,
                                                 int64_t ntiles, int64_t nrb, int64_t tiles_per_xcd,
@@ -90,7 +96,7 @@ __device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_
     const int64_t I = rb * 4 + wave;
     if (I >= nrows) return;
     const int64_t c = (tile * 64 + lane) * V;
-    const bool ok = c < ncols;  // with V = 2, ncols is even: c + 1 < ncols too
+    const bool ok = c < ncols;  // V divides ncols: c + V - 1 < ncols too
     const int64_t ld = ncols / V;
     const TV *__restrict__ Xc = (const TV *)(X + (ok ? c : 0));
     // the row's entries (of source chunk ch when the rows are chunked)
@@ -823,16 +829,19 @@ T *workspace(Ctx &c, int which) {
 template <typename T>
 void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st) {
     const int64_t nrows = s.l;
-    const int vec = sweep_vec(ncols);
-    // FP64: one launch, panels staged in LDS (FP32 gathers half the bytes
-    // per entry and measured faster with the plain sweep out of L2)
-    if (s.chunk == kPanelRows && sizeof(T) == 8) {
+    // FP32 takes 4 columns per lane (16-byte loads) when the rows allow it
+    const int vec = (sizeof(T) == 4 && ncols % 4 == 0) ? 4 : sweep_vec(ncols);
+    // one launch, panels staged in LDS: FP64, and FP32 with 4 columns per
+    // lane (16-byte row segments like FP64; with 2 columns per lane FP32
+    // measured faster with the plain sweep out of L2)
+    if (s.chunk == kPanelRows && (sizeof(T) == 8 || vec == 4)) {
         const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec);
         const int64_t nrb = (nrows + kPanelBlockRows - 1) / kPanelBlockRows;
         const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
         const unsigned grid = (unsigned)(kXcd * tpx * nrb);
-        auto f = vec == 2 ? (acc ? k_panel_sweep<T, true, 2> : k_panel_sweep<T, false, 2>)
-                          : (acc ? k_panel_sweep<T, true, 1> : k_panel_sweep<T, false, 1>);
+        auto f = vec == 4   ? (acc ? k_panel_sweep<T, true, 4> : k_panel_sweep<T, false, 4>)
+                 : vec == 2 ? (acc ? k_panel_sweep<T, true, 2> : k_panel_sweep<T, false, 2>)
+                            : (acc ? k_panel_sweep<T, true, 1> : k_panel_sweep<T, false, 1>);
         f<<<grid, kPanelThreads, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr, s.b_off,
                                           s.nch, s.b_col, Vals<T>::b(s), X, Y);
         TB_HIP(hipGetLastError());
@@ -845,8 +854,9 @@ void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, 
     const int nch = chunked ? s.nch : 1;
     for (int ch = 0; ch < nch; ++ch) {
         const bool a = acc || ch > 0;
-        auto f = vec == 2 ? (a ? k_row_sweep<T, true, 2> : k_row_sweep<T, false, 2>)
-                          : (a ? k_row_sweep<T, true, 1> : k_row_sweep<T, false, 1>);
+        auto f = vec == 4   ? (a ? k_row_sweep<T, true, 4> : k_row_sweep<T, false, 4>)
+                 : vec == 2 ? (a ? k_row_sweep<T, true, 2> : k_row_sweep<T, false, 2>)
+                            : (a ? k_row_sweep<T, true, 1> : k_row_sweep<T, false, 1>);
         f<<<grid, kBlock, 0, st>>>(nrows, ncols, ntiles, nrb, tpx, s.a_ptr,
                                    chunked ? s.b_col : s.a_col,
                                    chunked ? Vals<T>::b(s) : Vals<T>::a(s), X, Y,

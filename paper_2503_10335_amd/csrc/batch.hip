@@ -100,6 +100,21 @@ __device__ __forceinline__ void block_sums(const double (&acc)[kSV], int k, doub
 #define TB_SLOT_LOOP(e, lblk, t) \
     for (int64_t t = lblk * kB + threadIdx.x; t < e.n; t += (int64_t)e.nb * kB)
 
+// Kernels over the k vectors of a basis run a body templated on k, so that
+// each element's k loads are issued together (a loop guarded by i < k
+// issues them one branch at a time).  The arithmetic order is that of a
+// loop over i ascending.
+#define TB_K_DISPATCH(k, CALL)                                                            \
+    switch (k) {                                                                         \
+        case 1: CALL(1); break;   case 2: CALL(2); break;   case 3: CALL(3); break;      \
+        case 4: CALL(4); break;   case 5: CALL(5); break;   case 6: CALL(6); break;      \
+        case 7: CALL(7); break;   case 8: CALL(8); break;   case 9: CALL(9); break;      \
+        case 10: CALL(10); break; case 11: CALL(11); break; case 12: CALL(12); break;    \
+        case 13: CALL(13); break; case 14: CALL(14); break; case 15: CALL(15); break;    \
+        case 16: CALL(16); break; default: break;                                        \
+    }
+static_assert(kSV == 16, "TB_K_DISPATCH covers k = 1 .. 16");
+
 // H_KK from the per-string parts
 __device__ __forceinline__ double diag_at(const VDesc &e, int64_t t) {
     const int64_t ia = t / e.lb, ib = t - ia * e.lb;
@@ -258,101 +273,162 @@ __global__ __launch_bounds__(kB) void gv_diag(const VDesc *__restrict__ d, int n
 
 // x = V y, wx = W y, t = (wx - theta x) / (theta - H_KK) with a floor;
 // partial sums of |wx - theta x|^2 (H_KK read from the stored diagonal)
-__global__ __launch_bounds__(kB) void gv_ritz(const VDesc *__restrict__ d, int nd) {
-    int64_t lb;
-    const VDesc e = slot_of(d, nd, lb);
-    double acc[kSV] = {};
+template <int K>
+__device__ __forceinline__ void ritz_body(const VDesc &e, int64_t lb, double *acc) {
     TB_SLOT_LOOP(e, lb, t) {
+        double av[K], bv[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            av[i] = e.a[i][t];
+            bv[i] = e.b[i][t];
+        }
+        const double dk = e.in[t];
         double xv = 0.0, wv = 0.0;
 #pragma unroll
-        for (int i = 0; i < kSV; ++i)
-            if (i < e.k) {
-                xv += e.c[i] * e.a[i][t];
-                wv += e.c[i] * e.b[i][t];
-            }
+        for (int i = 0; i < K; ++i) {
+            xv += e.c[i] * av[i];
+            wv += e.c[i] * bv[i];
+        }
         const double r = wv - e.theta * xv;
         acc[0] += r * r;
-        double den = e.theta - e.in[t];
+        double den = e.theta - dk;
         if (fabs(den) < e.floor_) den = den < 0.0 ? -e.floor_ : e.floor_;
         e.o0[t] = xv;
         e.o1[t] = wv;
         e.o2[t] = r / den;
     }
+}
+
+__global__ __launch_bounds__(kB) void gv_ritz(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    double acc[kSV] = {};
+    if (e.k == 0) {  // empty basis: zero vectors
+        TB_SLOT_LOOP(e, lb, t) e.o0[t] = e.o1[t] = e.o2[t] = 0.0;
+    }
+#define TB_CALL(K) ritz_body<K>(e, lb, acc)
+    TB_K_DISPATCH(e.k, TB_CALL)
+#undef TB_CALL
     block_sums(acc, 1, e.partial + lb);
 }
 
 // o0 = sum_i c_i a_i, o1 = sum_i c_i b_i
-__global__ __launch_bounds__(kB) void gv_lincomb2(const VDesc *__restrict__ d, int nd) {
-    int64_t lb;
-    const VDesc e = slot_of(d, nd, lb);
+template <int K>
+__device__ __forceinline__ void lincomb2_body(const VDesc &e, int64_t lb) {
     TB_SLOT_LOOP(e, lb, t) {
+        double av[K], bv[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            av[i] = e.a[i][t];
+            bv[i] = e.b[i][t];
+        }
         double xv = 0.0, wv = 0.0;
 #pragma unroll
-        for (int i = 0; i < kSV; ++i)
-            if (i < e.k) {
-                xv += e.c[i] * e.a[i][t];
-                wv += e.c[i] * e.b[i][t];
-            }
+        for (int i = 0; i < K; ++i) {
+            xv += e.c[i] * av[i];
+            wv += e.c[i] * bv[i];
+        }
         e.o0[t] = xv;
         e.o1[t] = wv;
     }
 }
 
+__global__ __launch_bounds__(kB) void gv_lincomb2(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    if (e.k == 0) {  // empty basis: zero vectors
+        TB_SLOT_LOOP(e, lb, t) e.o0[t] = e.o1[t] = 0.0;
+    }
+#define TB_CALL(K) lincomb2_body<K>(e, lb)
+    TB_K_DISPATCH(e.k, TB_CALL)
+#undef TB_CALL
+}
+
 // partial[i][blk] = block's part of a_i . in, i < k, with `in` read once
+template <int K>
+__device__ __forceinline__ void dots_body(const VDesc &e, int64_t lb, double *acc) {
+    TB_SLOT_LOOP(e, lb, t) {
+        double av[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) av[i] = e.a[i][t];
+        const double x = e.in[t];
+#pragma unroll
+        for (int i = 0; i < K; ++i) acc[i] += av[i] * x;
+    }
+}
+
 __global__ __launch_bounds__(kB) void gv_dots(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
     double acc[kSV] = {};
-    TB_SLOT_LOOP(e, lb, t) {
-        const double x = e.in[t];
-#pragma unroll
-        for (int i = 0; i < kSV; ++i)
-            if (i < e.k) acc[i] += e.a[i][t] * x;
-    }
+#define TB_CALL(K) dots_body<K>(e, lb, acc)
+    TB_K_DISPATCH(e.k, TB_CALL)
+#undef TB_CALL
     block_sums(acc, e.k, e.partial + lb);
 }
 
 // o0 -= sum_i scal[src + i] a_i, then partial[i][blk] = a_i . o0: the
 // subtraction of the first Gram-Schmidt pass with the dot products of the
 // second
+template <int K>
+__device__ __forceinline__ void subdots_body(const VDesc &e, int64_t lb, const double *cf,
+                                             double *acc) {
+    TB_SLOT_LOOP(e, lb, t) {
+        double av[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) av[i] = e.a[i][t];
+        double v = e.o0[t];
+#pragma unroll
+        for (int i = 0; i < K; ++i) v -= cf[i] * av[i];
+        e.o0[t] = v;
+#pragma unroll
+        for (int i = 0; i < K; ++i) acc[i] += av[i] * v;
+    }
+}
+
 __global__ __launch_bounds__(kB) void gv_subdots(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
     double cf[kSV], acc[kSV] = {};
 #pragma unroll
     for (int i = 0; i < kSV; ++i) cf[i] = i < e.k ? e.scal[e.src + i] : 0.0;
-    TB_SLOT_LOOP(e, lb, t) {
-        double av[kSV];
-        double v = e.o0[t];
-#pragma unroll
-        for (int i = 0; i < kSV; ++i)
-            if (i < e.k) {
-                av[i] = e.a[i][t];
-                v -= cf[i] * av[i];
-            }
-        e.o0[t] = v;
-#pragma unroll
-        for (int i = 0; i < kSV; ++i)
-            if (i < e.k) acc[i] += av[i] * v;
-    }
+#define TB_CALL(K) subdots_body<K>(e, lb, cf, acc)
+    TB_K_DISPATCH(e.k, TB_CALL)
+#undef TB_CALL
     block_sums(acc, e.k, e.partial + lb);
 }
 
 // o0 -= sum_i scal[src + i] a_i, then partial[0][blk] = |o0|^2
+template <int K>
+__device__ __forceinline__ void subnorm_body(const VDesc &e, int64_t lb, const double *cf,
+                                             double *acc) {
+    TB_SLOT_LOOP(e, lb, t) {
+        double av[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) av[i] = e.a[i][t];
+        double v = e.o0[t];
+#pragma unroll
+        for (int i = 0; i < K; ++i) v -= cf[i] * av[i];
+        e.o0[t] = v;
+        acc[0] += v * v;
+    }
+}
+
 __global__ __launch_bounds__(kB) void gv_subnorm(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
     double cf[kSV], acc[kSV] = {};
 #pragma unroll
     for (int i = 0; i < kSV; ++i) cf[i] = i < e.k ? e.scal[e.src + i] : 0.0;
-    TB_SLOT_LOOP(e, lb, t) {
-        double v = e.o0[t];
-#pragma unroll
-        for (int i = 0; i < kSV; ++i)
-            if (i < e.k) v -= cf[i] * e.a[i][t];
-        e.o0[t] = v;
-        acc[0] += v * v;
+    if (e.k == 0) {  // |o0|^2 alone
+        TB_SLOT_LOOP(e, lb, t) {
+            const double v = e.o0[t];
+            acc[0] += v * v;
+        }
     }
+#define TB_CALL(K) subnorm_body<K>(e, lb, cf, acc)
+    TB_K_DISPATCH(e.k, TB_CALL)
+#undef TB_CALL
     block_sums(acc, 1, e.partial + lb);
 }
 
@@ -374,26 +450,37 @@ __global__ __launch_bounds__(kB) void gv_reduce(const VDesc *__restrict__ d, int
 }
 
 // o0 -= sum_i scal[src + i] a_i (and o1 -= sum_i scal[src + i] b_i)
+template <int K>
+__device__ __forceinline__ void subproj_body(const VDesc &e, int64_t lb, const double *cf) {
+    TB_SLOT_LOOP(e, lb, t) {
+        double av[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) av[i] = e.a[i][t];
+        double v = e.o0[t];
+#pragma unroll
+        for (int i = 0; i < K; ++i) v -= cf[i] * av[i];
+        e.o0[t] = v;
+        if (e.o1) {
+            double bv[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) bv[i] = e.b[i][t];
+            double w = e.o1[t];
+#pragma unroll
+            for (int i = 0; i < K; ++i) w -= cf[i] * bv[i];
+            e.o1[t] = w;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kB) void gv_subproj(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
     double cf[kSV];
 #pragma unroll
     for (int i = 0; i < kSV; ++i) cf[i] = i < e.k ? e.scal[e.src + i] : 0.0;
-    TB_SLOT_LOOP(e, lb, t) {
-        double v = e.o0[t];
-#pragma unroll
-        for (int i = 0; i < kSV; ++i)
-            if (i < e.k) v -= cf[i] * e.a[i][t];
-        e.o0[t] = v;
-        if (e.o1) {
-            double w = e.o1[t];
-#pragma unroll
-            for (int i = 0; i < kSV; ++i)
-                if (i < e.k) w -= cf[i] * e.b[i][t];
-            e.o1[t] = w;
-        }
-    }
+#define TB_CALL(K) subproj_body<K>(e, lb, cf)
+    TB_K_DISPATCH(e.k, TB_CALL)
+#undef TB_CALL
 }
 
 // o0 (and o1) *= 1 / |.| with |.| = sqrt(scal[src]), or by 0 when |.| <=

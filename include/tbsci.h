@@ -361,7 +361,8 @@ int tbsci_timing_read(tbsci_ctx *ctx, int kernel, int precision, double *total_m
 /*
  * flops = floating-point operations one launch of kernel `kernel` executes
  * (for the MFMA opposite-spin kernel: the padded matrix tiles, i.e. the
- * alpha link count of every row rounded up to a multiple of 4, times the
+ * alpha link count of every row rounded up to a multiple of 4 (of 16 for
+ * the FP32 sigma of the slab kernel, which runs k-steps in chunks), times the
  * (pq|rs) pairs rounded up to a multiple of 16, times the beta strings
  * rounded up to the column-tile width, times 2; for the other kernels the
  * same as the algorithmic count).  Returns TBSCI_E_INVAL for a bad index,

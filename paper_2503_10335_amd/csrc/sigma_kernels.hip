@@ -137,6 +137,11 @@ __device__ __forceinline__ void row_sweep_block(int64_t b, int64_t nrows, int64_
 
 // columns per lane for a sweep of ncols columns
 __host__ __device__ inline int sweep_vec(int64_t ncols) { return ncols % 2 == 0 ? 2 : 1; }
+// FP32 takes 4 columns per lane (16-byte loads) when the rows allow it
+template <typename T>
+__host__ __device__ inline int sweep_vec_of(int64_t ncols) {
+    return (sizeof(T) == 4 && ncols % 4 == 0) ? 4 : sweep_vec(ncols);
+}
 
 template <typename T, bool ACC, int V>
 __global__ __launch_bounds__(kBlock) void k_row_sweep(int64_t nrows, int64_t ncols, int64_t ntiles,
@@ -269,7 +274,11 @@ __device__ __forceinline__ int find_desc(const D *__restrict__ d, int nd, int64_
 template <typename T, bool ACC>
 __global__ __launch_bounds__(kBlock) void g_row_sweep(const SweepDesc *__restrict__ d, int nd) {
     const SweepDesc e = d[find_desc(d, nd, blockIdx.x)];
-    if (sweep_vec(e.ncols) == 2)
+    const int vec = sweep_vec_of<T>(e.ncols);
+    if (vec == 4)
+        row_sweep_block<T, ACC, 4>(blockIdx.x - e.blk0, e.nrows, e.ncols, e.ntiles, e.nrb, e.tpx,
+                                   e.ptr, e.col, (const T *)e.val, (const T *)e.X, (T *)e.Y);
+    else if (vec == 2)
         row_sweep_block<T, ACC, 2>(blockIdx.x - e.blk0, e.nrows, e.ncols, e.ntiles, e.nrb, e.tpx,
                                    e.ptr, e.col, (const T *)e.val, (const T *)e.X, (T *)e.Y);
     else
@@ -829,8 +838,7 @@ T *workspace(Ctx &c, int which) {
 template <typename T>
 void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st) {
     const int64_t nrows = s.l;
-    // FP32 takes 4 columns per lane (16-byte loads) when the rows allow it
-    const int vec = (sizeof(T) == 4 && ncols % 4 == 0) ? 4 : sweep_vec(ncols);
+    const int vec = sweep_vec_of<T>(ncols);
     // one launch, panels staged in LDS: FP64, and FP32 with 4 columns per
     // lane (16-byte row segments like FP64; with 2 columns per lane FP32
     // measured faster with the plain sweep out of L2)
@@ -1083,7 +1091,7 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
     int64_t bsa = 0, bsb = 0, bt1 = 0, bt2 = 0;
     auto sweep = [&](std::vector<SweepDesc> &v, int64_t &blk, const Spin &s, int64_t ncols,
                      const T *X, T *Y) {
-        const int vec = sweep_vec(ncols);
+        const int vec = sweep_vec_of<T>(ncols);
         const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec), nrb = (s.l + 3) / 4;
         const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
         v.push_back(SweepDesc{blk, s.l, ncols, ntiles, nrb, tpx, s.a_ptr, s.a_col, Vals<T>::a(s),
@@ -1244,8 +1252,12 @@ double executed_flops(Ctx &c, int kernel, int precision) {
     if (!slab && !tile) return 2.0 * (double)A.n_s * (double)B.n_s;
     std::vector<int64_t> ptr((size_t)A.l + 1);
     TB_HIP(hipMemcpy(ptr.data(), A.s_ptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    // links per row padded to whole k-steps of 4; the FP32 slab kernel runs
+    // k-steps in chunks of 4 (links padded to a multiple of 16)
+    const int64_t pad = slab && precision == TBSCI_FP32 ? 16 : 4;
     double kp = 0.0;
-    for (int64_t i = 0; i < A.l; ++i) kp += (double)(4 * ((ptr[i + 1] - ptr[i] + 3) / 4));
+    for (int64_t i = 0; i < A.l; ++i)
+        kp += (double)(pad * ((ptr[i + 1] - ptr[i] + pad - 1) / pad));
     const int w = slab ? 16 : kTW;  // columns per MFMA pass: slab or tile
     const double cols = (double)((B.l + w - 1) / w) * w;
     return 2.0 * kp * (16.0 * nmt) * cols;

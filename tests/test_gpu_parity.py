@@ -326,3 +326,23 @@ def test_sigma_tile_kernel_long_rows(env, shape):
     got32 = ctx.sigma(Cg.float(), precision=T.TBSCI_FP32).double().cpu().numpy()[rows]
     assert _rel(got32, ref)[0] <= 2e-5
     ctx.close()
+
+
+def test_executed_mfma_flops_accounting(env):
+    """The executed-flop count the benchmark reports for the MFMA
+    opposite-spin kernel, recomputed from the oracle's alpha link lists: per
+    alpha row, the link count padded to whole k-steps (4 links; chunks of 16
+    in the FP32 slab kernel) x the folded pairs padded to 16 x the beta
+    strings padded to the 16-column slab x 2."""
+    T, O, torch = env
+    p = PROBS["rand_m12_4_6"]
+    ctx = T.Context.from_problem(p)
+    ptr, _ = O.singles_with_diag(p.alpha, p.M)
+    K = np.diff(ptr)
+    P = p.M * (p.M + 1) // 2
+    rows16 = 16 * ((P + 15) // 16)
+    cols = 16 * ((len(p.beta) + 15) // 16)
+    for prec, pad in ((T.TBSCI_FP64, 4), (T.TBSCI_FP32, 16)):
+        kp = int(np.sum(pad * ((K + pad - 1) // pad)))
+        assert ctx.mfma_flops(prec) == 2.0 * kp * rows16 * cols
+    ctx.close()

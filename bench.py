@@ -152,6 +152,42 @@ def summarize_trace(trace_dir, out, commands, title):
     print("\n".join(lines))
 
 
+def summarize_counters(pmc_dir, out, commands, title):
+    """Per-kernel means of the counters of one rocprofv3 --pmc csv run, with
+    the kernel duration of each dispatch (from its timestamps) alongside."""
+    import csv
+    import glob
+    from collections import defaultdict
+    got = glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))
+    if len(got) != 1:
+        raise SystemExit(f"expected one counter_collection.csv in {pmc_dir}, found {got}")
+    vals = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(dict)
+    for r in csv.DictReader(open(got[0])):
+        k = short_name(r["Kernel_Name"])
+        vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur[k][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    names = sorted({c for k in vals for c in vals[k]})
+    lines = [f"# rocprofv3 counters: {title}", "# commands (run from the repository root):"]
+    lines += [f"#   {c}" for c in commands]
+    lines.append(f"#   python3 bench.py --summarize-counters {pmc_dir} --summary-out "
+                 f"{os.path.relpath(out, ROOT)} (with the command above as --command)")
+    lines.append("# per kernel: dispatches, mean duration (us, from the dispatch timestamps "
+                 "of the counter run), mean of each counter per dispatch")
+    order = sorted(vals, key=lambda k: -sum(dur[k].values()))
+    for k in order[:8]:
+        d = list(dur[k].values())
+        lines.append("")
+        lines.append(f"{k}  dispatches {len(d)}  mean_us {sum(d) / len(d):.1f}")
+        for c in names:
+            if c in vals[k]:
+                v = vals[k][c]
+                lines.append(f"  {c:32s} {sum(v) / len(v):.6e}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def measured_traffic(label: str, prec: str):
     """HBM bytes per launch from the committed counter summary, or None when
     there is none or the kernel source changed since it was taken."""
@@ -197,6 +233,9 @@ def parse():
                          "the profile summary and exit (no GPU)")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="summarize one rocprofv3 kernel-trace csv run and exit (no GPU)")
+    ap.add_argument("--summarize-counters", metavar="PMC_DIR",
+                    help="summarize one rocprofv3 --pmc csv run (per-kernel counter means) "
+                         "and exit (no GPU)")
     ap.add_argument("--title", default="kernel trace")
     ap.add_argument("--summary-out", default=PROFILE)
     ap.add_argument("--command", action="append", default=[],
@@ -211,6 +250,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.summary_out, args.command, args.title)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.summary_out, args.command, args.title)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -37,8 +37,8 @@ SIGMA_SRC = os.path.join(ROOT, "paper_2503_10335_amd", "csrc", "sigma_kernels.hi
 KERNEL_LABEL = {  # kernel-name prefix in the profiler -> (timing name, precision)
     "k_ab_slab<double": ("opposite_spin", "fp64"),
     "k_ab_slab<float": ("opposite_spin", "fp32"),
-    "k_ab_tile<double": ("opposite_spin", "fp64"),
-    "k_ab_tile<float": ("opposite_spin", "fp32"),
+    "k_ab_slabg<double": ("opposite_spin", "fp64"),
+    "k_ab_slabg<float": ("opposite_spin", "fp32"),
     "k_ab_direct<double": ("opposite_spin", "fp64"),
     "k_ab_direct<float": ("opposite_spin", "fp32"),
 }
@@ -52,7 +52,7 @@ def source_hash() -> str:
     parts = []
     for a, b in (("// ---------------------------------------------------------- opposite spin",
                   "// ---------------------------------------------------------------- driver"),
-                 ("template <typename T, int KS, int BOUND>\nvoid launch_ab_kb",
+                 ("// whether the global-fragment slab kernel takes a context",
                   "// Opposite-spin term, direct double sum")):
         i, j = text.find(a), text.find(b)
         if i < 0 or j < i:

@@ -18,7 +18,8 @@
 //                   block on MFMA, scatter through the beta single lists
 //                   into the output row (LDS atomics when it fits in LDS);
 //                   the slab kernel when the integral fragments and the row
-//                   fit in LDS together, else the tile kernel;
+//                   fit in LDS together, else the same kernel with the
+//                   fragments read from the L2-resident integral block;
 //   alpha sweep   : sparse rows of A_a times rows of C, one XCD per column
 //                   panel so each XCD's L2 holds its panel of C;
 //   beta sweep    : the same kernel on C^T, then a transpose-add.
@@ -354,36 +355,24 @@ struct Mfma<float> {
     }
 };
 
-// One block per output alpha row I; wave w owns MFMA M-tile w, i.e. 16
-// folded pairs rs, so blockDim = 64 * ceil(P / 16).  Per tile of kTW beta
-// columns:
+// Per output alpha row I and beta string c:
 //
 //   X[k][c]  = C[J_k][c]                     (gathered, k over the alpha links
-//                                              of I; double-buffered in LDS)
-//   Y[rs][c] = sum_k s_k V[pq_k][rs] X[k][c]  (MFMA; A fragments in registers)
+//                                              of I)
+//   Y[rs][c] = sum_k s_k V[pq_k][rs] X[k][c]  (MFMA over 16-pair M-tiles)
 //   row[I']  += s * Y[pair][J']  for every link (I', pair, s) of J' in the
 //               beta single lists (symmetric: the links of J' are the
 //               sources of I')
 //
 // Y never leaves the accumulators: the A rows are ordered so that register r
-// of a lane in lane group g holds pair 16 w + 4 r + g of its column, and the
+// of a lane in lane group g holds pair 16 m + 4 r + g of its column, and the
 // links are grouped by (tile, g), so each lane reads just its own links.
-// The next tile's X elements and link offsets are loaded into registers
-// while the current tile is multiplied; one barrier per tile.
 //
 // ROW selects where the output row accumulates: an FP64 row in LDS (FP64
 // LDS atomics, also for FP32 sigma: on gfx950 they are several times faster
 // than FP32 LDS atomics, and the row is rounded once at the end) for as many
 // beta strings as fit, the rest through global atomics on sigma; or, for an
 // FP32 row too long for that, a whole row of type T in LDS.
-#ifndef TB_AB_TW
-#define TB_AB_TW 32
-#endif
-constexpr int kTW = TB_AB_TW;   // beta columns per tile (16-column MFMA N-subtiles)
-constexpr int kNS = kTW / 16;
-constexpr int kXS = kTW + 1;    // LDS row stride of an X tile
-constexpr int kXPT = kTW / 4;   // X-tile elements per thread
-
 template <typename T>
 __device__ __forceinline__ int a_row_pair(int m);  // pair (within the tile) of A row m
 template <>
@@ -406,217 +395,13 @@ __device__ __forceinline__ auto pick4(const V4 &v, int r) {
 // whole row of type T in LDS
 enum { kRowF64 = 0, kRowT = 1, kRowSplit = 2 };
 
-struct AbLds {
-    size_t row, aj, x, total;
-    int64_t nrow;  // row entries held in LDS
-};
-
 constexpr size_t kLdsMax = 160 * 1024;
-
-// layout for a row of `nrow` entries of row_sz bytes (nrow < 0: as many as
-// fit in kLdsMax, at most lb)
-inline AbLds ab_lds(int64_t lb, int kmax, size_t sz, size_t row_sz, int64_t nrow = -1) {
-    AbLds L{};
-    size_t o = 0;
-    auto take = [&](size_t n) {
-        const size_t at = o;
-        o += (n + 15) & ~size_t(15);
-        return at;
-    };
-    L.aj = take((size_t)kmax * 4);
-    L.x = take(2 * (size_t)kmax * kXS * sz);
-    if (nrow < 0) {
-        const size_t room = o < kLdsMax ? (kLdsMax - o) / row_sz : 0;
-        nrow = std::min<int64_t>(lb, (int64_t)(room & ~size_t(1)));
-    }
-    L.nrow = nrow;
-    L.row = take((size_t)nrow * row_sz);
-    L.total = o;
-    return L;
-}
-
-template <typename T, int KS, int ROW>
-__device__ __forceinline__ void ab_tile_row(const int64_t I, int64_t lb, int P, int nmt,
-                                            const AbLds L, const int64_t *__restrict__ sa_ptr,
-                                            const Ent *__restrict__ sa_ent,
-                                            const int64_t *__restrict__ sb_ptr,
-                                            const Ent *__restrict__ sb_grp,
-                                            const int32_t *__restrict__ sb_off,
-                                            const T *__restrict__ V, const T *__restrict__ C,
-                                            T *__restrict__ S) {
-    using M = Mfma<T>;
-    using R = typename std::conditional<ROW == kRowT, T, double>::type;
-    const int64_t nrow = ROW == kRowSplit ? L.nrow : lb;
-    extern __shared__ __align__(16) unsigned char smem[];
-    R *row = (R *)(smem + L.row);
-    int32_t *aj = (int32_t *)(smem + L.aj);
-    T *xbuf = (T *)(smem + L.x);
-
-    const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int g = lane >> 4, cl = lane & 15;
-    const int64_t a0 = sa_ptr[I];
-    const int K = (int)(sa_ptr[I + 1] - a0);
-    const int nks = (K + 3) >> 2, Kp = nks * 4;
-    const int nx = Kp * kTW;
-    const int ng = 4 * nmt;
-    const int key = 4 * wave + g;  // this lane's link group
-
-    for (int64_t i = tid; i < nrow; i += nthr) row[i] = R(0);
-    for (int k = tid; k < Kp; k += nthr) aj[k] = k < K ? sa_ent[a0 + k].j : -1;
-
-    // A fragments: lane holds U[k = 4 ks + g][row cl] of this wave's M-tile
-    T ua[KS];
-    {
-        const int m = wave * 16 + a_row_pair<T>(cl);
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            T a = T(0);
-            const int k = 4 * ks + g;
-            if (ks < nks && k < K && m < P) {
-                const Ent e = sa_ent[a0 + k];
-                const T v = V[(int64_t)(e.o >> 16) * P + m];
-                a = ((e.o >> 12) & 1u) ? -v : v;
-            }
-            ua[ks] = a;
-        }
-    }
-    __syncthreads();
-
-    T xr[kXPT];
-    auto load_x = [&](int64_t j0) {
-#pragma unroll
-        for (int u = 0; u < kXPT; ++u) {
-            const int i = tid + u * nthr;
-            T v = T(0);
-            if (i < nx) {
-                const int k = i / kTW, cc = i - k * kTW;
-                const int32_t J = aj[k];
-                if (J >= 0 && j0 + cc < lb) v = C[(int64_t)J * lb + j0 + cc];
-            }
-            xr[u] = v;
-        }
-    };
-    auto store_x = [&](T *xt) {
-#pragma unroll
-        for (int u = 0; u < kXPT; ++u) {
-            const int i = tid + u * nthr;
-            if (i < nx) {
-                const int k = i / kTW, cc = i - k * kTW;
-                xt[k * kXS + cc] = xr[u];
-            }
-        }
-    };
-    // link ranges of this lane's group for its columns of a tile
-    int64_t lb0[kNS];
-    int32_t ln0[kNS];
-    auto load_off = [&](int64_t j0) {
-#pragma unroll
-        for (int ns = 0; ns < kNS; ++ns) {
-            const int64_t col = j0 + ns * 16 + cl;
-            lb0[ns] = 0;
-            ln0[ns] = 0;
-            if (wave < nmt && col < lb) {
-                const int32_t *off = sb_off + col * (ng + 1) + key;
-                const int32_t o0 = off[0];
-                lb0[ns] = sb_ptr[col] + o0;
-                ln0[ns] = off[1] - o0;
-            }
-        }
-    };
-
-    const int64_t ntile = (lb + kTW - 1) / kTW;
-    load_x(0);
-    store_x(xbuf);
-    load_off(0);
-    __syncthreads();
-    for (int64_t t = 0; t < ntile; ++t) {
-        T *xt = xbuf + (size_t)(t & 1) * Kp * kXS;
-        const int64_t j0 = t * kTW;
-        // this tile's link ranges (offsets arrived during the previous tile)
-        int64_t eb[kNS];
-        int32_t en[kNS];
-#pragma unroll
-        for (int ns = 0; ns < kNS; ++ns) {
-            eb[ns] = lb0[ns];
-            en[ns] = ln0[ns];
-        }
-        if (t + 1 < ntile) {
-            load_x(j0 + kTW);
-            load_off(j0 + kTW);
-        }
-        typename M::acc_t acc[kNS];
-#pragma unroll
-        for (int ns = 0; ns < kNS; ++ns) acc[ns] = typename M::acc_t{0, 0, 0, 0};
-        if (wave < nmt) {
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                if (ks < nks) {
-                    const int k = 4 * ks + g;
-#pragma unroll
-                    for (int ns = 0; ns < kNS; ++ns)
-                        acc[ns] = M::mma(ua[ks], xt[k * kXS + ns * 16 + cl], acc[ns]);
-                }
-        }
-        // scatter this lane's links: register r holds pair 16 w + 4 r + g
-#pragma unroll
-        for (int ns = 0; ns < kNS; ++ns) {
-            for (int32_t x = 0; x < en[ns]; ++x) {
-                const Ent e = sb_grp[eb[ns] + x];
-                T v = pick4(acc[ns], (int)(((e.o >> 16) & 15) >> 2));
-                if ((e.o >> 12) & 1u) v = -v;
-                if (ROW != kRowSplit || e.j < nrow)
-                    atomicAdd(&row[e.j], (R)v);
-                else
-                    atomicAdd(&S[I * lb + e.j], v);
-            }
-        }
-        if (t + 1 < ntile) store_x(xbuf + (size_t)((t + 1) & 1) * Kp * kXS);
-        __syncthreads();
-    }
-    // (the strings from nrow on received their links by global atomics)
-    for (int64_t i = tid; i < nrow; i += nthr) S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
-}
-
-template <typename T, int KS, int ROW, int BOUND>
-__global__ __launch_bounds__(BOUND) void k_ab_tile(int64_t lb, int P, int nmt, AbLds L,
-                                                  const int64_t *__restrict__ sa_ptr,
-                                                  const Ent *__restrict__ sa_ent,
-                                                  const int64_t *__restrict__ sb_ptr,
-                                                  const Ent *__restrict__ sb_grp,
-                                                  const int32_t *__restrict__ sb_off,
-                                                  const T *__restrict__ V, const T *__restrict__ C,
-                                                  T *__restrict__ S) {
-    ab_tile_row<T, KS, ROW>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off, V,
-                            C, S);
-}
-
-// one problem of a grouped opposite-spin launch: blocks [blk0, blk0 + l_alpha)
-struct AbDesc {
-    int64_t blk0, lb;
-    AbLds L;
-    const int64_t *sa_ptr;
-    const Ent *sa_ent;
-    const int64_t *sb_ptr;
-    const Ent *sb_grp;
-    const int32_t *sb_off;
-    const void *V, *C;
-    void *S;
-};
-
-template <typename T, int KS, int ROW, int BOUND>
-__global__ __launch_bounds__(BOUND) void g_ab_tile(const AbDesc *__restrict__ d, int nd, int P,
-                                                  int nmt) {
-    const AbDesc e = d[find_desc(d, nd, blockIdx.x)];
-    ab_tile_row<T, KS, ROW>(blockIdx.x - e.blk0, e.lb, P, nmt, e.L, e.sa_ptr, e.sa_ent, e.sb_ptr,
-                            e.sb_grp, e.sb_off, (const T *)e.V, (const T *)e.C, (T *)e.S);
-}
 
 // Slab kernel: one output row I per block, waves independent of each other.
 // The A fragments of every M-tile (the signed integral rows U of the alpha
 // links of I) are staged in LDS once per row.  A wave takes 16-column slabs
 // of beta strings off a counter in LDS; per slab it loads its B fragments
-// (C[J_k][16 columns], the X of the tile kernel) straight from global
+// (C[J_k][16 columns]) straight from global
 // memory into registers and runs the M-tiles one after another: MFMA over
 // the links, then the scatter of the tile's accumulators through the beta
 // single lists into the FP64 row in LDS.  There is no barrier between
@@ -795,6 +580,196 @@ __global__ __launch_bounds__(kSlabBlock) void k_ab_slab(int64_t lb, int P, int n
                        S);
 }
 
+// Slab kernel with the A fragments read from global memory, for rows whose
+// fragments do not fit LDS beside the output row.  The sign of each alpha
+// link is folded into its C fragment, so an A fragment is a plain element
+// of the folded integral block V (L2-resident): lane l of k-step ks reads
+// V[pq_k][16 m + row(l)] with k = 4 ks + l/16.  LDS holds the output row
+// (whole, split, or of type T: see ROW above) and the link columns.
+struct SlabgLds {
+    size_t row, aj, apq, ctr, total;
+    int64_t nrow;  // row entries held in LDS
+};
+
+inline SlabgLds slabg_lds(int64_t lb, int nks, size_t row_sz, int64_t nrow = -1) {
+    SlabgLds L{};
+    size_t o = 0;
+    auto take = [&](size_t n) {
+        const size_t at = o;
+        o += (n + 15) & ~size_t(15);
+        return at;
+    };
+    const int nk4 = (nks + 3) / 4 * 4;
+    L.aj = take((size_t)nk4 * 4 * 4);
+    L.apq = take((size_t)nk4 * 4 * 4);
+    L.ctr = take(4);
+    if (nrow < 0) {
+        const size_t room = o < kLdsMax ? (kLdsMax - o) / row_sz : 0;
+        nrow = std::min<int64_t>(lb, (int64_t)(room & ~size_t(1)));
+    }
+    L.nrow = nrow;
+    L.row = take((size_t)nrow * row_sz);
+    L.total = o;
+    return L;
+}
+
+template <typename T, int KS, int ROW>
+__device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P, int nmt,
+                                             const SlabgLds L, const int64_t *__restrict__ sa_ptr,
+                                             const Ent *__restrict__ sa_ent,
+                                             const int64_t *__restrict__ sb_ptr,
+                                             const Ent *__restrict__ sb_grp,
+                                             const int32_t *__restrict__ sb_off,
+                                             const T *__restrict__ V, const T *__restrict__ C,
+                                             T *__restrict__ S) {
+    using M = Mfma<T>;
+    using R = typename std::conditional<ROW == kRowT, T, double>::type;
+    const int64_t nrow = ROW == kRowSplit ? L.nrow : lb;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R *row = (R *)(smem + L.row);
+    int32_t *aj = (int32_t *)(smem + L.aj);
+    int32_t *apq = (int32_t *)(smem + L.apq);
+    int *ctr = (int *)(smem + L.ctr);
+
+    const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const int g = lane >> 4, cl = lane & 15;
+    const int64_t a0 = sa_ptr[I];
+    const int K = (int)(sa_ptr[I + 1] - a0);
+    const int nks = (K + 3) >> 2;
+    const int ng = 4 * nmt;
+    constexpr int G = 4;  // A fragments loaded per group, one group ahead
+
+    // link columns, laid out [lane group][k-step] so that a lane's four
+    // consecutive k-steps are one 16-byte LDS read: aj = source row J (or
+    // -1), apq = pq_k P (the V row offset) | sign << 30
+    const int nk4 = (nks + 3) & ~3;
+    for (int64_t i = tid; i < nrow; i += nthr) row[i] = R(0);
+    for (int k = tid; k < 4 * nk4; k += nthr) {
+        int32_t J = -1, pq = 0;
+        if (k < K) {
+            const Ent e = sa_ent[a0 + k];
+            J = e.j;
+            pq = (int32_t)((e.o >> 16) * (uint32_t)P) | (int32_t)(((e.o >> 12) & 1u) << 30);
+        }
+        const int kk = (k & 3) * nk4 + (k >> 2);  // k = 4 ks + g -> [g][ks]
+        aj[kk] = J;
+        apq[kk] = pq;
+    }
+    if (tid == 0) *ctr = 0;
+    __syncthreads();
+
+    const int32_t *ajg = aj + g * nk4, *apg = apq + g * nk4;
+    uint32_t sgn = 0;  // link signs of this lane's k-steps
+    for (int ks = 0; ks < nks; ++ks) sgn |= (uint32_t)((apg[ks] >> 30) & 1) << ks;
+
+    const int r16 = a_row_pair<T>(cl);
+    const int64_t nslab = (lb + 15) >> 4;
+    for (;;) {
+        int sl = 0;
+        if (lane == 0) sl = atomicAdd(ctr, 1);
+        sl = __builtin_amdgcn_readfirstlane(sl);
+        if (sl >= nslab) break;
+        const int64_t col = (int64_t)sl * 16 + cl;
+        const bool cin = col < lb;
+        T b[KS];
+        {
+            int32_t J[KS];
+#pragma unroll
+            for (int q = 0; q < KS / 4; ++q) {
+                int4 j4 = make_int4(-1, -1, -1, -1);
+                if (4 * q < nks) j4 = *(const int4 *)(ajg + 4 * q);
+                J[4 * q] = j4.x;
+                J[4 * q + 1] = j4.y;
+                J[4 * q + 2] = j4.z;
+                J[4 * q + 3] = j4.w;
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                T v = T(0);
+                if (J[ks] >= 0 && cin) v = C[(int64_t)J[ks] * lb + col];
+                b[ks] = ((sgn >> ks) & 1u) ? -v : v;
+            }
+        }
+        const int32_t *off = sb_off + (cin ? col : 0) * (ng + 1) + g;
+        const int64_t base = cin ? sb_ptr[col] : 0;
+        int32_t n0 = 0, n1 = 0;
+        if (cin) {
+            n0 = off[0];
+            n1 = off[1];
+        }
+        for (int m = 0; m < nmt; ++m) {
+            const int32_t o0 = n0, o1 = n1;
+            Ent e0{0, 0}, e1{0, 0}, e2{0, 0}, e3{0, 0};
+            const bool h0 = o0 < o1, h1 = o0 + 1 < o1, h2 = o0 + 2 < o1, h3 = o0 + 3 < o1;
+            if (h0) e0 = sb_grp[base + o0];
+            if (h1) e1 = sb_grp[base + o0 + 1];
+            if (h2) e2 = sb_grp[base + o0 + 2];
+            if (h3) e3 = sb_grp[base + o0 + 3];
+            if (cin && m + 1 < nmt) {
+                n0 = off[4 * (m + 1)];
+                n1 = off[4 * (m + 1) + 1];
+            }
+            // this lane's column of V for tile m (row 0 stands in for pairs
+            // past P; their fragments are zeroed)
+            const int pr = 16 * m + r16;
+            const bool pin = pr < P;
+            const T *Vm = V + (pin ? pr : 0);
+            // A fragments of k-step group q: V[pq_k P + pr] for the group's
+            // four k-steps (padding steps read row 0; their C fragments are 0)
+            auto ldg = [&](int q, T *a) {
+                const int4 o4 = *(const int4 *)(apg + 4 * q);
+                a[0] = pin ? Vm[o4.x & 0xffff] : T(0);
+                a[1] = pin ? Vm[o4.y & 0xffff] : T(0);
+                a[2] = pin ? Vm[o4.z & 0xffff] : T(0);
+                a[3] = pin ? Vm[o4.w & 0xffff] : T(0);
+            };
+            typename M::acc_t acc = typename M::acc_t{0, 0, 0, 0};
+            T an[G] = {};
+            if (nks > 0) ldg(0, an);
+#pragma unroll
+            for (int q = 0; q < KS / G; ++q)
+                if (G * q < nks) {
+                    T a[G];
+#pragma unroll
+                    for (int u = 0; u < G; ++u) a[u] = an[u];
+                    if (G * (q + 1) < nks) ldg(q + 1, an);
+#pragma unroll
+                    for (int u = 0; u < G; ++u)
+                        if (G * q + u < nks) acc = M::mma(a[u], b[G * q + u], acc);
+                }
+            auto put = [&](const Ent &e) {
+                T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
+                if ((e.o >> 12) & 1u) v = -v;
+                if (ROW != kRowSplit || e.j < nrow)
+                    atomicAdd(&row[e.j], (R)v);
+                else
+                    atomicAdd(&S[I * lb + e.j], v);
+            };
+            if (h0) put(e0);
+            if (h1) put(e1);
+            if (h2) put(e2);
+            if (h3) put(e3);
+            for (int32_t x = o0 + 4; x < o1; ++x) put(sb_grp[base + x]);
+        }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < nrow; i += nthr) S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
+}
+
+template <typename T, int KS, int ROW>
+__global__ __launch_bounds__(kSlabBlock) void k_ab_slabg(int64_t lb, int P, int nmt, SlabgLds L,
+                                                        const int64_t *__restrict__ sa_ptr,
+                                                        const Ent *__restrict__ sa_ent,
+                                                        const int64_t *__restrict__ sb_ptr,
+                                                        const Ent *__restrict__ sb_grp,
+                                                        const int32_t *__restrict__ sb_off,
+                                                        const T *__restrict__ V,
+                                                        const T *__restrict__ C,
+                                                        T *__restrict__ S) {
+    ab_slabg_row<T, KS, ROW>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off,
+                             V, C, S);
+}
+
 // one problem of a grouped slab launch: blocks [blk0, blk0 + l_alpha)
 struct SlabDesc {
     int64_t blk0, lb;
@@ -888,37 +863,36 @@ void allow_lds(Ctx &c, const void *f, size_t bytes) {
     c.lds_set.emplace_back(f, bytes);
 }
 
-template <typename T, int KS, int BOUND>
-void launch_ab_kb(Ctx &c, const T *C, T *S, hipStream_t st) {
+// whether the global-fragment slab kernel takes a context: k-steps within
+// its register budget, and V row offsets pq P that fit 16 bits
+bool slabg_fits(const Ctx &c) {
+    const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
+    return ks <= 32 && c.P * c.P < 65536;
+}
+
+template <typename T, int KS>
+void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     const int P = c.P, nmt = (P + 15) / 16;
+    const int ks = std::max((A.max_s + 3) / 4, 1);
     // an FP64 row (split when the whole row does not fit); FP32 sigma with
     // a long row keeps a whole FP32 row instead when that fits
     int row = kRowF64;
-    AbLds L = ab_lds(B.l, 4 * KS, sizeof(T), 8);
+    SlabgLds L = slabg_lds(B.l, ks, 8);
     if (L.nrow < B.l) {
         row = kRowSplit;
-        if (sizeof(T) < 8 && ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T), B.l).total <= kLdsMax) {
+        if (sizeof(T) < 8 && slabg_lds(B.l, ks, sizeof(T), B.l).total <= kLdsMax) {
             row = kRowT;
-            L = ab_lds(B.l, 4 * KS, sizeof(T), sizeof(T), B.l);
+            L = slabg_lds(B.l, ks, sizeof(T), B.l);
         }
     }
-    auto f = row == kRowF64 ? k_ab_tile<T, KS, kRowF64, BOUND>
-             : row == kRowT ? k_ab_tile<T, KS, kRowT, BOUND>
-                            : k_ab_tile<T, KS, kRowSplit, BOUND>;
+    auto f = row == kRowF64 ? k_ab_slabg<T, KS, kRowF64>
+             : row == kRowT ? k_ab_slabg<T, KS, kRowT>
+                            : k_ab_slabg<T, KS, kRowSplit>;
     if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
-    f<<<(unsigned)A.l, 64 * nmt, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
-                                                B.g_ent, B.g_off, Vals<T>::V(c), C, S);
+    f<<<(unsigned)A.l, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
+                                                  B.g_ent, B.g_off, Vals<T>::V(c), C, S);
     TB_HIP(hipGetLastError());
-}
-
-// a tighter launch bound leaves more registers per lane (no spills)
-template <typename T, int KS>
-void launch_ab_ks(Ctx &c, const T *C, T *S, hipStream_t st) {
-    if ((c.P + 15) / 16 <= 10)
-        launch_ab_kb<T, KS, 640>(c, C, S, st);
-    else
-        launch_ab_kb<T, KS, 1024>(c, C, S, st);
 }
 
 // KS instance of the slab kernel for a context (0: it does not apply)
@@ -953,19 +927,19 @@ bool launch_ab(Ctx &c, const T *C, T *S, hipStream_t st) {
         case 24: launch_ab_slab<T, 24>(c, C, S, st); return true;
         default: break;
     }
+    if (!slabg_fits(c)) return false;
     const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
-    const int nmt = (c.P + 15) / 16;
-    if (ks > 32 || nmt > 16) return false;
-    // every X-tile element needs a prefetch register
-    if (4 * ks * kTW > kXPT * 64 * nmt) return false;
-#define TB_KS(n)                                \
-    if (ks <= n) {                              \
-        launch_ab_ks<T, n>(c, C, S, st);        \
-        return true;                            \
-    }
-    TB_KS(4) TB_KS(8) TB_KS(12) TB_KS(16) TB_KS(20) TB_KS(24) TB_KS(28) TB_KS(32)
-#undef TB_KS
-    return false;
+    if (ks <= 8)
+        launch_ab_slabg<T, 8>(c, C, S, st);
+    else if (ks <= 16)
+        launch_ab_slabg<T, 16>(c, C, S, st);
+    else if (ks <= 24)
+        launch_ab_slabg<T, 24>(c, C, S, st);
+    else if (ks <= 28)
+        launch_ab_slabg<T, 28>(c, C, S, st);
+    else
+        launch_ab_slabg<T, 32>(c, C, S, st);
+    return true;
 }
 
 // Opposite-spin term, direct double sum (general fallback):
@@ -1029,43 +1003,6 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms) {
     timing_mark(c, 3, prec, st);
 }
 
-// KS instance used by the tile kernel for a context (0: direct kernel)
-int ab_ks(const Ctx &c) {
-    const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
-    const int nmt = (c.P + 15) / 16;
-    if (ks > 32 || nmt > 16 || 4 * ks * kTW > kXPT * 64 * nmt) return 0;
-    return (ks + 3) / 4 * 4;
-}
-
-template <typename T, int KS, int BOUND>
-void launch_ab_group_kb(const AbDesc *dd, int nd, int64_t blocks, int P, size_t lds, Ctx &c0,
-                        hipStream_t st) {
-    const int nmt = (P + 15) / 16;
-    auto f = g_ab_tile<T, KS, kRowF64, BOUND>;
-    if (lds > 64 * 1024) allow_lds(c0, (const void *)f, lds);
-    f<<<(unsigned)blocks, 64 * nmt, lds, st>>>(dd, nd, P, nmt);
-    TB_HIP(hipGetLastError());
-}
-
-template <typename T>
-void launch_ab_group(const AbDesc *dd, int nd, int64_t blocks, int P, int KS, size_t lds, Ctx &c0,
-                     hipStream_t st) {
-    const bool small = (P + 15) / 16 <= 10;
-#define TB_G(n)                                                                      \
-    case n:                                                                          \
-        if (small)                                                                   \
-            launch_ab_group_kb<T, n, 640>(dd, nd, blocks, P, lds, c0, st);           \
-        else                                                                         \
-            launch_ab_group_kb<T, n, 1024>(dd, nd, blocks, P, lds, c0, st);          \
-        break;
-    switch (KS) {
-        TB_G(4) TB_G(8) TB_G(12) TB_G(16) TB_G(20) TB_G(24) TB_G(28) TB_G(32)
-        default:
-            throw Error(TBSCI_E_DEVICE, "no grouped opposite-spin kernel for this shape");
-    }
-#undef TB_G
-}
-
 template <typename T>
 void launch_slab_group(const SlabDesc *dd, int nd, int64_t blocks, int P, int KS, size_t lds,
                        Ctx &c0, hipStream_t st) {
@@ -1104,14 +1041,6 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
         v.push_back(TransDesc{blk, R, Cn, ntc, in, out});
         blk += ntr * ntc;
     };
-    // opposite-spin groups: problems with the same P and KS share a launch
-    struct Group {
-        int P, KS;
-        size_t lds;
-        int64_t blocks;
-        std::vector<AbDesc> d;
-    };
-    std::vector<Group> groups;
     struct SlabGroup {
         int P, KS;
         size_t lds;
@@ -1145,31 +1074,13 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
             g->lds = std::max(g->lds, L.total);
             continue;
         }
-        const int KS = ab_ks(c);
-        const AbLds L = ab_lds(B.l, 4 * std::max(KS, 1), sizeof(T), 8);
-        if (KS == 0 || L.nrow < B.l) {  // grouped kernels hold whole FP64 rows
-            direct.push_back(i);
-            continue;
-        }
-        Group *g = nullptr;
-        for (auto &x : groups)
-            if (x.P == c.P && x.KS == KS) g = &x;
-        if (!g) {
-            groups.push_back(Group{c.P, KS, 0, 0, {}});
-            g = &groups.back();
-        }
-        g->d.push_back(AbDesc{g->blocks, B.l, L, A.s_ptr, A.s_ent, B.s_ptr, B.g_ent, B.g_off,
-                              Vals<T>::V(c), C[i], S[i]});
-        g->blocks += A.l;
-        g->lds = std::max(g->lds, L.total);
+        direct.push_back(i);  // single-problem opposite-spin kernel
     }
     if (n == 0) return;
     const SweepDesc *dsa = ar.stage(sa.data(), sa.size());
     const SweepDesc *dsb = ar.stage(sb.data(), sb.size());
     const TransDesc *dt1 = ar.stage(t1.data(), t1.size());
     const TransDesc *dt2 = ar.stage(t2.data(), t2.size());
-    std::vector<const AbDesc *> dg;
-    for (auto &g : groups) dg.push_back(ar.stage(g.d.data(), g.d.size()));
     std::vector<const SlabDesc *> dsg;
     for (auto &g : sgroups) dsg.push_back(ar.stage(g.d.data(), g.d.size()));
     ar.flush(st);
@@ -1181,9 +1092,6 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
     for (size_t k = 0; k < sgroups.size(); ++k)
         launch_slab_group<T>(dsg[k], (int)sgroups[k].d.size(), sgroups[k].blocks, sgroups[k].P,
                              sgroups[k].KS, sgroups[k].lds, *ctx[0], st);
-    for (size_t k = 0; k < groups.size(); ++k)
-        launch_ab_group<T>(dg[k], (int)groups[k].d.size(), groups[k].blocks, groups[k].P,
-                           groups[k].KS, groups[k].lds, *ctx[0], st);
     for (int i : direct) {  // single-problem opposite-spin kernels
         Ctx &c = *ctx[i];
         if (launch_ab<T>(c, C[i], S[i], st)) continue;
@@ -1238,28 +1146,24 @@ void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st,
 }
 
 // Floating-point operations one launch of kernel `kernel` executes: for the
-// MFMA opposite-spin kernel the padded tiles (K rounded up to the 4-deep
-// k-step, pairs to 16-row M-tiles, beta columns to kTW-wide tiles); for
-// the sweeps and the direct fallback the multiply-adds of their sums.
+// MFMA opposite-spin kernels the padded tiles (K rounded up to the 4-deep
+// k-step, or to chunks of 4 k-steps in the FP32 slab kernel; pairs to
+// 16-row M-tiles; beta columns to 16-column slabs); for the sweeps and the
+// direct fallback the multiply-adds of their sums.
 double executed_flops(Ctx &c, int kernel, int precision) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     if (kernel == 0) return 2.0 * (double)A.n_a * (double)B.l;
     if (kernel == 1) return 2.0 * (double)B.n_a * (double)A.l;
-    const int ks = std::max((A.max_s + 3) / 4, 1);
     const int nmt = (c.P + 15) / 16;
     const bool slab = slab_ks(c, precision == TBSCI_FP32 ? sizeof(float) : sizeof(double)) > 0;
-    const bool tile = ks <= 32 && nmt <= 16 && 4 * ks * kTW <= kXPT * 64 * nmt;
-    if (!slab && !tile) return 2.0 * (double)A.n_s * (double)B.n_s;
+    if (!slab && !slabg_fits(c)) return 2.0 * (double)A.n_s * (double)B.n_s;
     std::vector<int64_t> ptr((size_t)A.l + 1);
     TB_HIP(hipMemcpy(ptr.data(), A.s_ptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-    // links per row padded to whole k-steps of 4; the FP32 slab kernel runs
-    // k-steps in chunks of 4 (links padded to a multiple of 16)
     const int64_t pad = slab && precision == TBSCI_FP32 ? 16 : 4;
     double kp = 0.0;
     for (int64_t i = 0; i < A.l; ++i)
         kp += (double)(pad * ((ptr[i + 1] - ptr[i] + pad - 1) / pad));
-    const int w = slab ? 16 : kTW;  // columns per MFMA pass: slab or tile
-    const double cols = (double)((B.l + w - 1) / w) * w;
+    const double cols = (double)((B.l + 15) / 16) * 16;
     return 2.0 * kp * (16.0 * nmt) * cols;
 }
 

@@ -279,11 +279,12 @@ def _shell_alpha(M, N):
     return np.array(out, dtype=np.uint64)
 
 
-def test_sigma_tile_kernel_many_links(env):
-    """An alpha string with more alpha links than the slab kernel takes (the
-    reference string of a single-excitation shell at M = 20 has 100 singles
-    plus 10 occupations): the opposite-spin term runs in the tile kernel,
-    whole FP64 row in LDS.  FP64 and FP32 sigma against the oracle."""
+def test_sigma_global_fragments_many_links(env):
+    """An alpha string with more links than the slab kernel's LDS fragments
+    take (the reference string of a single-excitation shell at M = 20 has 100
+    singles plus 10 occupations, 28 k-steps): the opposite-spin term reads its
+    integral fragments from global memory, whole FP64 row in LDS.  FP64 and
+    FP32 sigma against the oracle."""
     T, O, torch = env
     M, N = 20, 10
     h, eri = W.integrals(M, 41)
@@ -305,14 +306,14 @@ def test_sigma_tile_kernel_many_links(env):
 
 
 @pytest.mark.parametrize("shape", [(24, 18000), (16, 21000)])
-def test_sigma_tile_kernel_long_rows(env, shape):
+def test_sigma_global_fragments_long_rows(env, shape):
     """Beta lists too long for the slab kernel's LDS (an FP64 row of 18000 or
-    21000 strings plus FP64 fragments): FP64 sigma in the tile kernel, with
-    the whole FP64 row in LDS (18000) or the row split between LDS and
-    global atomics (21000).  FP32 sigma: the slab kernel (18000; its
-    fragments are half the size) or the tile kernel with a whole FP32 row
-    in LDS (21000).  Eight alpha rows, first and last included, against the
-    oracle."""
+    21000 strings plus FP64 fragments): FP64 sigma reads its fragments from
+    global memory, with the whole FP64 row in LDS (18000) or the row split
+    between LDS and global atomics (21000).  FP32 sigma: fragments in LDS
+    (18000; they are half the size) or from global memory with a whole FP32
+    row in LDS (21000).  Eight alpha rows, first and last included, against
+    the oracle."""
     T, O, torch = env
     la, lb = shape
     p = W.random_selection(18, 9, 9, la, lb, seed=43)

@@ -347,3 +347,30 @@ def test_executed_mfma_flops_accounting(env):
         kp = int(np.sum(pad * ((K + pad - 1) // pad)))
         assert ctx.mfma_flops(prec) == 2.0 * kp * rows16 * cols
     ctx.close()
+
+
+def test_sigma_direct_fallback(env):
+    """A shape neither MFMA kernel takes in FP64: M = 23 (P = 276, so the V
+    row offsets of the global-fragment kernel would not fit 16 bits) with all
+    253 two-electron alpha strings (44 links each) and 7000 beta strings (the
+    FP64 fragments and row overflow LDS): the opposite-spin term runs in the
+    direct double-sum kernel.  FP32 takes the slab kernel with 18 M-tiles.
+    Six alpha rows against the oracle."""
+    T, O, torch = env
+    p = W.random_selection(23, 2, 4, 253, 7000, seed=47)
+    assert len(p.alpha) == 253 and len(p.beta) == 7000
+    ctx = T.Context.from_problem(p)
+    # the executed-flop count names the kernel: the direct kernel's is the
+    # plain double sum over all alpha and beta links
+    na = int(np.diff(O.singles_with_diag(p.alpha, p.M)[0]).sum())
+    nb = int(np.diff(O.singles_with_diag(p.beta, p.M)[0]).sum())
+    assert ctx.mfma_flops(T.TBSCI_FP64) == 2.0 * na * nb
+    C = np.random.default_rng(8).normal(size=(ctx.l_alpha, ctx.l_beta))
+    rows = np.array([0, 17, 100, 181, 222, 252])
+    ref = O.Space.of(p).sigma(C, rows=rows, nthreads=16)
+    Cg = torch.from_numpy(C).cuda()
+    e, m = _rel(ctx.sigma(Cg).cpu().numpy()[rows], ref)
+    assert e <= 1e-12 and m <= 1e-12
+    got32 = ctx.sigma(Cg.float(), precision=T.TBSCI_FP32).double().cpu().numpy()[rows]
+    assert _rel(got32, ref)[0] <= 2e-5
+    ctx.close()

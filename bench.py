@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the TPB sigma build sigma = H*C on one MI355X.
 
-Workload: the selected TPB space with M = 16 spatial orbitals,
-N_alpha = N_beta = 8, the 3,000 lowest-ranked alpha and beta strings of the
-12,870 (ranking: sum of occupied h_pp plus seeded N(0, 0.1) noise), i.e.
-9.0e6 determinants; integrals from seed 1002, selection seed 2002.
+Headline workload (the largest configuration that fits one GPU): the
+complete TPB space with M = 18 spatial orbitals, N_alpha = N_beta = 9, all
+48,620 alpha and 48,620 beta strings, i.e. 2.36e9 determinants (18.9 GB per
+FP64 vector); integrals from seed 1004.
 
 A step is one FP64 sigma build over the whole space (all three kernels),
 with C resident in HBM.  ``value`` is determinants per second,
 n_det * steps / elapsed.  Also reported in the same JSON line: the FP32
-sigma rate, Davidson time to solution in FP64 and in mixed precision with
-|E - E_ref|, per-kernel event timings, the roofline entry of the dominant
-kernel, and the CPU oracle timed on a bounded row sample on the host cores.
+sigma rate, per-kernel event timings, the roofline entry of the dominant
+kernel, the sigma rates of the smaller selected workloads, Davidson time to
+solution in FP64 and in mixed precision on a named smaller workload, the
+serving mix, and the CPU oracle timed on a bounded row sample of the
+headline workload on the host cores.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
@@ -32,7 +34,12 @@ PEAK = {  # MI355X published peaks
 }
 
 
-PROFILE = os.path.join(ROOT, "profiles", "sigma_kernels_sel_m16.txt")
+def profile_path(workload: str) -> str:
+    """Committed counter summary of the sigma kernels on one workload."""
+    return os.path.join(ROOT, "profiles", f"sigma_kernels_{workload}.txt")
+
+
+PROFILE = None  # override of profile_path() (tests)
 SIGMA_SRC = os.path.join(ROOT, "paper_2503_10335_amd", "csrc", "sigma_kernels.hip")
 KERNEL_LABEL = {  # kernel-name prefix in the profiler -> (timing name, precision)
     "k_ab_slab<double": ("opposite_spin", "fp64"),
@@ -67,10 +74,13 @@ def short_name(name: str) -> str:
     return re.sub(r"\(.*", "", name).strip()
 
 
-def summarize(trace_dir, fetch_dir, write_dir, out, commands):
+def summarize(trace_dir, fetch_dir, write_dir, out, commands,
+              title="sigma kernels, FP64 and FP32 sigma builds"):
     """Write a short text summary of three rocprofv3 csv runs (kernel trace,
     FETCH_SIZE pass, WRITE_SIZE pass) of this benchmark, including the HBM
-    bytes per launch of the opposite-spin kernel scaled by the copy kernel."""
+    bytes per launch of the opposite-spin kernel scaled by the copy kernel.
+    Each (label, precision) must be served by one kernel in the run (else
+    SystemExit): its traffic line names that kernel."""
     import csv
     import glob
     from collections import defaultdict
@@ -93,8 +103,7 @@ def summarize(trace_dir, fetch_dir, write_dir, out, commands):
     copy_f = max(ctr["FETCH_SIZE"]["__amd_rocclr_copyBuffer"]) * 1024.0
     copy_w = max(ctr["WRITE_SIZE"]["__amd_rocclr_copyBuffer"]) * 1024.0
     kf, kw = COPY_BYTES / copy_f, COPY_BYTES / copy_w
-    lines = ["# rocprofv3 summary: sigma kernels, selected TPB space M=16, N=8,",
-             "# 3000 x 3000 strings (9.0e6 determinants), FP64 and FP32 sigma builds",
+    lines = [f"# rocprofv3 summary: {title}",
              "# commands (run from the repository root):"]
     lines += [f"#   {c}" for c in commands]
     lines.append(f"#   python3 bench.py --summarize {trace_dir} {fetch_dir} {write_dir} "
@@ -121,10 +130,13 @@ def summarize(trace_dir, fetch_dir, write_dir, out, commands):
         lines.append(f"{k[:34]:34s} {len(v):3d} {fb / 1e6:10.2f} {wb / 1e6:10.2f}")
         for pre, (label, prec) in KERNEL_LABEL.items():
             if k.startswith(pre):
-                traffic[(label, prec)] = fb + wb
+                if (label, prec) in traffic:
+                    raise SystemExit(f"two kernels serve {label} {prec} in this run: "
+                                     f"{traffic[(label, prec)][1]} and {k}")
+                traffic[(label, prec)] = (fb + wb, k)
     lines.append("")
-    for (label, prec), b in sorted(traffic.items()):
-        lines.append(f"traffic {label} {prec} {b:.0f}")
+    for (label, prec), (b, k) in sorted(traffic.items()):
+        lines.append(f"traffic {label} {prec} {b:.0f} {k.replace(' ', '')}")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -188,21 +200,22 @@ def summarize_counters(pmc_dir, out, commands, title):
     print("\n".join(lines))
 
 
-def measured_traffic(label: str, prec: str):
-    """HBM bytes per launch from the committed counter summary, or None when
-    there is none or the kernel source changed since it was taken."""
+def measured_traffic(label: str, prec: str, workload: str = "fci_m18"):
+    """(HBM bytes per launch, kernel name) from the committed counter summary
+    of the workload, or (None, None) when there is none or the kernel source
+    changed since it was taken."""
     try:
-        text = open(PROFILE).read().splitlines()
+        text = open(PROFILE or profile_path(workload)).read().splitlines()
     except OSError:
-        return None
+        return None, None
     rec = dict(l.split(None, 1) for l in text if l.startswith("source_sha256 "))
     if rec.get("source_sha256", "").strip() != source_hash():
-        return None
+        return None, None
     for l in text:
         f = l.split()
-        if len(f) == 4 and f[0] == "traffic" and f[1] == label and f[2] == prec:
-            return float(f[3])
-    return None
+        if len(f) == 5 and f[0] == "traffic" and f[1] == label and f[2] == prec:
+            return float(f[3]), f[4]
+    return None, None
 
 
 def parse():
@@ -210,14 +223,31 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sel_m16")
-    ap.add_argument("--no-davidson", action="store_true")
+    ap.add_argument("--workload", default="fci_m18", help="headline sigma workload")
+    ap.add_argument("--extra-workloads", default="sel_m16,sel_m20",
+                    help="comma-separated workloads whose FP64/FP32 sigma rates are reported "
+                         "beside the headline ('' for none)")
+    ap.add_argument("--extra-steps", type=int, default=10)
+    ap.add_argument("--davidson-workload", default="sel_m16",
+                    help="workload of the Davidson leg ('' skips it)")
+    ap.add_argument("--davidson-n-max", type=int, default=8)
+    ap.add_argument("--davidson-tol", type=float, default=1e-4,
+                    help="FP64 residual norm that ends the timed solves")
+    ap.add_argument("--davidson-sector", type=int, default=0,
+                    help="spin-flip sector of the timed solves (0: both, the lowest state)")
+    ap.add_argument("--davidson-storage", type=int, default=0,
+                    help="0 auto, 1 full, 2 lean vector storage")
+    ap.add_argument("--davidson-max-iter", type=int, default=600)
     ap.add_argument("--no-davidson-ref", action="store_true",
                     help="skip the FP64 reference solve to |r| <= 1e-6 (for spaces where it "
                          "takes too long); the mixed energy is then compared with the FP64 one")
+    ap.add_argument("--davidson-only", action="store_true",
+                    help="run only the Davidson leg (and its oracle check)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=32,
+                    help="smallest number of sampled alpha rows of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic for scaling profiler byte counters)")
@@ -237,64 +267,63 @@ def parse():
                     help="summarize one rocprofv3 --pmc csv run (per-kernel counter means) "
                          "and exit (no GPU)")
     ap.add_argument("--title", default="kernel trace")
-    ap.add_argument("--summary-out", default=PROFILE)
+    ap.add_argument("--summary-out", default=None)
     ap.add_argument("--command", action="append", default=[],
                     help="command line recorded in the summary (repeatable)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.summarize:
-        summarize(*args.summarize, args.summary_out, args.command)
-        return
-    if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.summary_out, args.command, args.title)
-        return
-    if args.summarize_counters:
-        summarize_counters(args.summarize_counters, args.summary_out, args.command, args.title)
-        return
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (one process holds the whole CI "
-              "vector); --gpus must be 1.", file=sys.stderr, flush=True)
-        sys.exit(2)
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
-    import numpy as np
-    import torch
 
-    from paper_2503_10335_amd import tbsci as T
-    from paper_2503_10335_amd import workloads as W
+def cpu_model():
+    try:
+        for l in open("/proc/cpuinfo"):
+            if l.startswith("model name"):
+                return l.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    if not os.path.exists(T.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
-    T.load()
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda", 0)
 
-    prob = W.config(args.workload)
+def host_threads():
+    """Host threads the oracle may use: the process's CPU share
+    (OMP_NUM_THREADS when set, else the usable cores)."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def kernel_table(ks):
+    out = {}
+    for k in ks:
+        avg_s = k["total_ms"] / max(k["launches"], 1) * 1e-3
+        out[k["name"]] = dict(avg_ms=avg_s * 1e3, launches=k["launches"],
+                              alg_tflops=k["flops"] / avg_s / 1e12 if avg_s > 0 else None,
+                              compulsory_gbs=k["bytes"] / avg_s / 1e9 if avg_s > 0 else None,
+                              flops_per_launch=k["flops"], bytes_per_launch=k["bytes"])
+    return out
+
+
+def sigma_leg(T, torch, W, name, steps, warmup, fp32=True, keep=False):
+    """FP64 (and FP32) sigma builds on one workload with C resident in HBM;
+    returns the rates, per-kernel event timings and (keep) the context and
+    the FP64 C and sigma."""
+    prob = W.config(name)
     t0 = time.perf_counter()
     ctx = T.Context.from_problem(prob, device=0)
     create_s = time.perf_counter() - t0
-    n_det = ctx.n_det
-    print(f"# workload {args.workload}: l_alpha={ctx.l_alpha} l_beta={ctx.l_beta} "
-          f"n_det={n_det} create {create_s:.3f}s", file=sys.stderr, flush=True)
-
-    if args.copy_calibration:
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    C64 = torch.from_numpy(W.random_vector(ctx.l_alpha, ctx.l_beta, seed=7)).to(dev)
+    log(f"workload {name}: l_alpha={ctx.l_alpha} l_beta={ctx.l_beta} n_det={ctx.n_det} "
+        f"create {create_s:.3f}s")
+    C64 = W.random_vector_device(ctx.l_alpha, ctx.l_beta, seed=7, device="cuda:0")
     S64 = torch.empty_like(C64)
-    C32 = C64.float()
-    S32 = torch.empty_like(C32)
-    stream = torch.cuda.current_stream()
 
-    def timed(C, S, prec, steps, warmup):
+    def timed(C, S, prec):
         for _ in range(warmup):
             ctx.sigma(C, out=S, precision=prec)
         torch.cuda.synchronize()
@@ -308,169 +337,302 @@ def main():
         T.tbsci_timing_enable(ctx.handle, False)
         return el, kernels
 
-    el64, k64 = timed(C64, S64, T.TBSCI_FP64, args.steps, args.warmup)
-    el32, k32 = (1.0, None) if args.fp64_only else timed(C32, S32, T.TBSCI_FP32, args.steps,
-                                                          args.warmup)
-    value = n_det * args.steps / el64
-    print(f"# fp64 sigma {1e3 * el64 / args.steps:.3f} ms/step, fp32 "
-          f"{1e3 * el32 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    el64, k64 = timed(C64, S64, T.TBSCI_FP64)
+    out = dict(prob=prob, create_s=create_s, n_det=ctx.n_det, el64=el64, k64=k64,
+               dets_per_s=ctx.n_det * steps / el64, ms_per_step=1e3 * el64 / steps)
+    log(f"{name} fp64 sigma {out['ms_per_step']:.3f} ms/step")
+    if fp32:
+        C32 = C64.float()
+        S32 = torch.empty_like(C32)
+        el32, k32 = timed(C32, S32, T.TBSCI_FP32)
+        out.update(el32=el32, k32=k32, fp32_dets_per_s=ctx.n_det * steps / el32,
+                   fp32_ms_per_step=1e3 * el32 / steps)
+        log(f"{name} fp32 sigma {out['fp32_ms_per_step']:.3f} ms/step")
+        del C32, S32
+    if keep:
+        out.update(ctx=ctx, C64=C64, S64=S64)
+    else:
+        ctx.close()
+        del C64, S64
+        torch.cuda.empty_cache()
+    return out
 
-    def kernel_table(ks, prec):
-        out = {}
-        for k in ks:
-            avg_s = k["total_ms"] / max(k["launches"], 1) * 1e-3
-            out[k["name"]] = dict(avg_ms=avg_s * 1e3, launches=k["launches"],
-                                  alg_tflops=k["flops"] / avg_s / 1e12 if avg_s > 0 else None,
-                                  compulsory_gbs=k["bytes"] / avg_s / 1e9 if avg_s > 0 else None,
-                                  flops_per_launch=k["flops"], bytes_per_launch=k["bytes"])
-        return out
 
-    kt64 = kernel_table(k64, T.TBSCI_FP64)
-    kt32 = kernel_table(k32, T.TBSCI_FP32) if k32 else None
-    # dominant kernel: the opposite-spin term, a dense contraction on FP64
-    # MFMA.  achieved = algorithmic flops of the direct double sum
-    # (2 n_s_alpha n_s_beta) over the event-timed average launch; the flops
-    # the padded MFMA tiles execute are reported beside it.
+def roofline_of(T, ctx, k64, workload):
+    """Roofline entry of the dominant kernel of the FP64 sigma (the
+    opposite-spin term, a dense contraction on FP64 MFMA): achieved =
+    algorithmic flops of the direct double sum (2 n_s_alpha n_s_beta) over
+    the event-timed average launch; the flops the padded MFMA tiles execute
+    are reported beside it."""
     dom = max(k64, key=lambda k: k["total_ms"])
     dom_avg = dom["total_ms"] / dom["launches"] * 1e-3
     achieved = dom["flops"] / dom_avg / 1e12
-    roofline = {
+    traffic, kname = measured_traffic(dom["name"], "fp64", workload)
+    r = {
         "kernel": dom["name"],
         "bound": "mfma" if dom["name"] == "opposite_spin" else "alu",
         "achieved": achieved,
         "peak": PEAK["fp64_tflops"],
         "unit": "TFLOP/s",
         "frac": achieved / PEAK["fp64_tflops"],
-        "traffic": measured_traffic(dom["name"], "fp64"),
+        "traffic": traffic,
+        "traffic_kernel": kname,
         "avg_launch_ms": dom_avg * 1e3,
         "flops_per_launch": dom["flops"],
     }
     if dom["name"] == "opposite_spin":
         ex = ctx.mfma_flops(T.TBSCI_FP64)
-        roofline["executed_mfma_flops_per_launch"] = ex
-        roofline["executed_mfma_tflops"] = ex / dom_avg / 1e12
-        roofline["executed_frac"] = ex / dom_avg / 1e12 / PEAK["fp64_tflops"]
-    if roofline["traffic"] is not None:
-        roofline["traffic_gbs"] = roofline["traffic"] / dom_avg / 1e9
+        r["executed_mfma_flops_per_launch"] = ex
+        r["executed_mfma_tflops"] = ex / dom_avg / 1e12
+        r["executed_frac"] = ex / dom_avg / 1e12 / PEAK["fp64_tflops"]
+    if traffic is not None:
+        r["traffic_gbs"] = traffic / dom_avg / 1e9
+        r["compulsory_bytes_per_launch"] = dom["bytes"]
+    return r
+
+
+def davidson_leg(T, torch, W, args):
+    """Time to solution in FP64 and in mixed precision on one workload
+    (both spin-flip sectors unless one is asked for), against an FP64
+    reference solve to |r| <= 1e-6; the eigenvectors go to host memory for
+    the oracle check."""
+    name = args.davidson_workload
+    prob = W.config(name)
+    ctx = T.Context.from_problem(prob, device=0)
+    kw = dict(n_max=args.davidson_n_max, max_iter=args.davidson_max_iter,
+              sector=args.davidson_sector, storage=args.davidson_storage)
+    ref = None
+    if not args.no_davidson_ref:
+        ref, _ = ctx.davidson(tol_resid=1e-6, want_vector=False, **kw)
+        log(f"davidson reference {ref['energy']:.10f} ({ref['iters']} builds)")
+    d64, X = ctx.davidson(tol_resid=args.davidson_tol, **kw)
+    eig_host = {"fp64": (d64["energy"], X)}
+    log(f"davidson fp64 {d64['t_total_s']:.3f}s ({d64['iters']} builds) E {d64['energy']:.10f}")
+    # the FP32 phase runs to half the target residual; FP64 sigma builds
+    # then certify (and if needed finish) the solve
+    dmx, X2 = ctx.davidson(tol_resid=args.davidson_tol, precision=T.TBSCI_MIXED,
+                           fp32_switch_resid=0.5 * args.davidson_tol, **kw)
+    eig_host["mixed"] = (dmx["energy"], X2)
+    log(f"davidson mixed {dmx['t_total_s']:.3f}s ({dmx['iters_fp32']}+{dmx['iters_fp64']} "
+        f"builds) E {dmx['energy']:.10f}")
+    e_ref = ref["energy"] if ref else None
+
+    def err(e):
+        return abs(e - e_ref) if ref else None
+
+    def leg(d):
+        return dict(time_s=d["t_total_s"], sigma_s=d["t_sigma_s"], iters=d["iters"],
+                    iters_fp32=d["iters_fp32"], iters_fp64=d["iters_fp64"],
+                    energy=d["energy"], energy_fp64_check=d["energy_fp64_check"],
+                    energy_other_sector=None if d["energy_other"] != d["energy_other"]
+                    else d["energy_other"], sector=d["sector"], lean=d["lean"],
+                    abs_err=err(d["energy"]), resid=d["resid_norm"], converged=d["converged"])
+
+    res = {
+        "workload": name,
+        "stop": f"FP64 residual norm <= {args.davidson_tol:g} (energy error ~ |r|^2/gap)",
+        "n_max": args.davidson_n_max,
+        "sectors": "both spin-flip sectors, lowest returned" if args.davidson_sector == 0
+        else f"sector {args.davidson_sector} only",
+        "e_ref": e_ref, "ref_resid": ref["resid_norm"] if ref else None,
+        "ref_iters": ref["iters"] if ref else None,
+        "fp64": leg(d64),
+        "mixed": leg(dmx),
+        "abs_diff_mixed_vs_fp64": abs(dmx["energy"] - d64["energy"]),
+        "speedup_mixed_vs_fp64": d64["t_total_s"] / dmx["t_total_s"],
+    }
+    return res, prob, ctx, eig_host
+
+
+def oracle_eigen_check(O, prob, eig_host, threads, n_rows=16):
+    """The oracle's (H x)_K on seeded alpha rows against E x_K: no component
+    of H x - E x can exceed the solver's residual norm."""
+    import numpy as np
+    sp = O.Space.of(prob)
+    la = len(prob.alpha)
+    rng = np.random.default_rng(98)
+    srows = np.sort(rng.choice(la, size=min(n_rows, la), replace=False))
+    need = sp.linked_rows(srows)
+    out = {}
+    for leg, (energy, X) in eig_host.items():
+        xs = X[torch_index(need, X)].cpu().numpy()
+        hx = sp.sigma_rows_from(srows, xs, need, nthreads=threads)
+        pos = np.searchsorted(need, srows)
+        out[leg] = float(np.abs(hx - energy * xs[pos]).max())
+    return out, len(srows)
+
+
+def torch_index(rows, X):
+    import torch
+    return torch.as_tensor(rows, dtype=torch.long, device=X.device)
+
+
+def cpu_baseline(O, prob, C64, S64, args):
+    """The oracle (plain C, OpenMP) on a row sample of the headline
+    workload: at least --cpu-rows seeded alpha rows over the full beta
+    range, more if the target CPU time allows; with the process's host
+    threads and with one thread.  The sample doubles as a parity check of
+    the timed GPU sigma."""
+    import numpy as np
+    threads = host_threads()
+    sp = O.Space.of(prob)
+    la, lb = len(prob.alpha), len(prob.beta)
+    rng = np.random.default_rng(99)
+
+    def run(rows, nthreads):
+        need = sp.linked_rows(rows)
+        Cs = C64[torch_index(need, C64)].cpu().numpy()
+        t0 = time.perf_counter()
+        ref = sp.sigma_rows_from(rows, Cs, need, nthreads=nthreads)
+        return ref, time.perf_counter() - t0
+
+    probe = np.sort(rng.choice(la, size=min(4, la), replace=False))
+    _, tp = run(probe, threads)
+    n_rows = int(min(la, max(args.cpu_rows, len(probe) * args.cpu_seconds / max(tp, 1e-3))))
+    rows = np.sort(rng.choice(la, size=n_rows, replace=False))
+    ref_rows, tc = run(rows, threads)
+    got = S64[torch_index(rows, S64)].cpu().numpy()
+    err = float(np.linalg.norm(got - ref_rows) / np.linalg.norm(ref_rows))
+    one = rows[:1]
+    _, t1 = run(one, 1)
+    log(f"cpu oracle {n_rows} rows in {tc:.1f}s on {threads} threads, 1 row in {t1:.1f}s on "
+        f"1 thread, parity {err:.2e}")
+    return {
+        "value": n_rows * lb / tc,
+        "unit": "dets/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{n_rows} seeded alpha rows x {lb} beta columns of the headline space "
+                  f"({n_rows * lb} determinants), FP64 determinant-driven Slater-Condon "
+                  f"oracle, {tc:.1f} s on {threads} threads",
+        "cpu_model": cpu_model(),
+        "one_thread_dets_per_s": lb / t1,
+        "one_thread_sample": f"1 alpha row x {lb} beta columns, {t1:.1f} s",
+        "gpu_vs_sample_rel_err": err,
+    }
+
+
+def main():
+    global PROFILE
+    args = parse()
+    if args.summarize:
+        summarize(*args.summarize, args.summary_out or profile_path("fci_m18"), args.command,
+                  args.title)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.summary_out, args.command, args.title)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.summary_out, args.command, args.title)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (one process holds the whole CI "
+              "vector); --gpus must be 1.", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2503_10335_amd import tbsci as T
+    from paper_2503_10335_amd import workloads as W
+
+    if not os.path.exists(T.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    T.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     result = {
         "metric": "H·C dets/s; Davidson time to 1e-6 Eh, FP32-MFMA vs FP64; p50/p99 solve latency",
-        "value": value,
-        "unit": "dets/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * el64 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
+        "unit": "dets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
+    }
+    if args.davidson_only:
+        from oracle import oracle as O
+        dv, prob, ctx, eig = davidson_leg(T, torch, W, args)
+        if not args.no_cpu_baseline:
+            chk, nr = oracle_eigen_check(O, prob, eig, host_threads())
+            for leg, v in chk.items():
+                dv[leg]["sampled_residual"] = v
+            dv["oracle_check"] = (f"sampled_residual = max_K |(H x)_K - E x_K|, (H x)_K from "
+                                  f"the oracle on {nr} seeded alpha rows; bounded by resid")
+        result["davidson"] = dv
+        result["value"] = None
+        result["config"] = {"workload": f"{args.davidson_workload} (Davidson leg only)"}
+        ctx.close()
+        print(json.dumps(result), flush=True)
+        return
+
+    head = sigma_leg(T, torch, W, args.workload, args.steps, args.warmup,
+                     fp32=not args.fp64_only, keep=True)
+    prob, ctx = head["prob"], head["ctx"]
+    result.update({
+        "value": head["dets_per_s"],
+        "ms_per_step": head["ms_per_step"],
         "config": {
-            "workload": f"{args.workload}: selected TPB space, M={prob.M}, "
-                        f"N_alpha=N_beta={prob.n_alpha}, {ctx.l_alpha} x {ctx.l_beta} strings, "
-                        f"{n_det} determinants",
+            "workload": f"{args.workload}: TPB space, M={prob.M}, N_alpha=N_beta={prob.n_alpha}, "
+                        f"{ctx.l_alpha} x {ctx.l_beta} strings, {ctx.n_det} determinants, "
+                        f"one FP64 sigma build per step",
             "M": prob.M, "n_alpha": prob.n_alpha, "n_beta": prob.n_beta,
-            "l_alpha": ctx.l_alpha, "l_beta": ctx.l_beta, "n_det": n_det,
+            "l_alpha": ctx.l_alpha, "l_beta": ctx.l_beta, "n_det": ctx.n_det,
             "parallelism": "1 GPU",
         },
-        "fp32_sigma_dets_per_s": n_det * args.steps / el32,
-        "fp32_ms_per_step": 1e3 * el32 / args.steps,
-        "create_s": create_s,
-        "kernels_fp64": kt64,
-        "kernels_fp32": kt32,
-        "roofline": roofline,
-    }
-
-    if not args.no_davidson:
-        ref = None
-        if not args.no_davidson_ref:
-            ref, _ = ctx.davidson(tol_resid=1e-6, n_max=8, max_iter=600, want_vector=False)
-        # the eigenvectors go to host memory for the oracle check of the
-        # cpu_baseline leg
-        d64, X = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600)
-        eig_host = {"fp64": (d64["energy"], X.cpu().numpy())}
-        del X
-        # the FP32 phase runs to half the target residual; FP64 sigma builds
-        # then certify (and if needed finish) the solve
-        dmx, X = ctx.davidson(tol_resid=1e-4, n_max=8, max_iter=600, precision=T.TBSCI_MIXED,
-                              fp32_switch_resid=5e-5)
-        eig_host["mixed"] = (dmx["energy"], X.cpu().numpy())
-        del X
-        e_ref = ref["energy"] if ref else None
-
-        def err(e):
-            return abs(e - e_ref) if ref else None
-
-        result["davidson"] = {
-            "stop": "FP64 residual norm <= 1e-4 (energy error ~ |r|^2/gap)",
-            "e_ref": e_ref, "ref_resid": ref["resid_norm"] if ref else None,
-            "ref_iters": ref["iters"] if ref else None,
-            "fp64": dict(time_s=d64["t_total_s"], sigma_s=d64["t_sigma_s"], iters=d64["iters"],
-                         energy=d64["energy"], abs_err=err(d64["energy"]),
-                         resid=d64["resid_norm"], converged=d64["converged"]),
-            "mixed": dict(time_s=dmx["t_total_s"], sigma_s=dmx["t_sigma_s"], iters=dmx["iters"],
-                          iters_fp32=dmx["iters_fp32"], iters_fp64=dmx["iters_fp64"],
-                          energy=dmx["energy"], abs_err=err(dmx["energy"]),
-                          abs_diff_vs_fp64=abs(dmx["energy"] - d64["energy"]),
-                          resid=dmx["resid_norm"], converged=dmx["converged"]),
-            "speedup_mixed_vs_fp64": d64["t_total_s"] / dmx["t_total_s"],
-        }
-        print(f"# davidson fp64 {d64['t_total_s']:.3f}s ({d64['iters']} it), mixed "
-              f"{dmx['t_total_s']:.3f}s ({dmx['iters_fp32']}+{dmx['iters_fp64']} it), "
-              f"E64={d64['energy']:.10f} Emixed={dmx['energy']:.10f}", file=sys.stderr,
-              flush=True)
-
+        "fp32_sigma_dets_per_s": head.get("fp32_dets_per_s"),
+        "fp32_ms_per_step": head.get("fp32_ms_per_step"),
+        "create_s": head["create_s"],
+        "kernels_fp64": kernel_table(head["k64"]),
+        "kernels_fp32": kernel_table(head["k32"]) if "k32" in head else None,
+        "roofline": roofline_of(T, ctx, head["k64"], args.workload),
+    })
     if not args.no_cpu_baseline:
         from oracle import oracle as O
-        threads = min(os.cpu_count() or 1, 16)
-        sp = O.Space.of(prob)
-        Ch = C64.cpu().numpy()
-        rng = np.random.default_rng(99)
-        probe = np.sort(rng.choice(ctx.l_alpha, size=min(16, ctx.l_alpha), replace=False))
-        t0 = time.perf_counter()
-        sp.sigma(Ch, rows=probe, nthreads=threads)
-        tp = time.perf_counter() - t0
-        n_rows = int(min(ctx.l_alpha, max(len(probe), len(probe) * args.cpu_seconds / max(tp, 1e-3))))
-        rows = np.sort(rng.choice(ctx.l_alpha, size=n_rows, replace=False))
-        t0 = time.perf_counter()
-        ref_rows = sp.sigma(Ch, rows=rows, nthreads=threads)
-        tc = time.perf_counter() - t0
-        # the sample doubles as a parity check of the timed GPU sigma
-        S64h = S64.cpu().numpy()[rows]
-        err = float(np.linalg.norm(S64h - ref_rows) / np.linalg.norm(ref_rows))
-        result["cpu_baseline"] = {
-            "value": n_rows * ctx.l_beta / tc,
-            "unit": "dets/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n_rows} seeded alpha rows x {ctx.l_beta} beta columns of the same "
-                      f"space ({n_rows * ctx.l_beta} determinants), FP64 determinant-driven "
-                      f"Slater-Condon oracle, {tc:.1f} s",
-            "gpu_vs_sample_rel_err": err,
-        }
-        print(f"# cpu oracle {n_rows} rows in {tc:.1f}s on {threads} threads, parity {err:.2e}",
-              file=sys.stderr, flush=True)
-        if "davidson" in result:
-            # the oracle's (H x)_K on 16 seeded alpha rows against E x_K: no
-            # component of H x - E x can exceed the solver's residual norm
-            srows = np.sort(rng.choice(ctx.l_alpha, size=min(16, ctx.l_alpha), replace=False))
-            need = sp.linked_rows(srows)
-            for leg, (energy, xh) in eig_host.items():
-                hx = sp.sigma_rows_from(srows, xh[need], need, nthreads=threads)
-                dev = float(np.abs(hx - energy * xh[srows]).max())
-                result["davidson"][leg]["sampled_residual"] = dev
-            result["davidson"]["oracle_check"] = (
-                f"sampled_residual = max_K |(H x)_K - E x_K|, (H x)_K from the oracle on "
-                f"{len(srows)} seeded alpha rows x {ctx.l_beta} beta columns; bounded by resid")
-            print(f"# oracle check of the eigenvectors: max |Hx - Ex| fp64 "
-                  f"{result['davidson']['fp64']['sampled_residual']:.2e}, mixed "
-                  f"{result['davidson']['mixed']['sampled_residual']:.2e}", file=sys.stderr,
-                  flush=True)
-
+        result["cpu_baseline"] = cpu_baseline(O, prob, head["C64"], head["S64"], args)
     ctx.close()
+    del head
+    torch.cuda.empty_cache()
+
+    extra = {}
+    for name in [w for w in args.extra_workloads.split(",") if w]:
+        e = sigma_leg(T, torch, W, name, args.extra_steps, min(args.warmup, 3),
+                      fp32=not args.fp64_only)
+        extra[name] = dict(n_det=e["n_det"], fp64_dets_per_s=e["dets_per_s"],
+                           fp64_ms_per_step=e["ms_per_step"],
+                           fp32_dets_per_s=e.get("fp32_dets_per_s"),
+                           fp32_ms_per_step=e.get("fp32_ms_per_step"),
+                           kernels_fp64=kernel_table(e["k64"]),
+                           kernels_fp32=kernel_table(e["k32"]) if "k32" in e else None)
+    if extra:
+        result["other_workloads"] = extra
+
+    if args.davidson_workload:
+        dv, dprob, dctx, eig = davidson_leg(T, torch, W, args)
+        if not args.no_cpu_baseline:
+            from oracle import oracle as O
+            chk, nr = oracle_eigen_check(O, dprob, eig, host_threads())
+            for leg, v in chk.items():
+                dv[leg]["sampled_residual"] = v
+            dv["oracle_check"] = (f"sampled_residual = max_K |(H x)_K - E x_K|, (H x)_K from "
+                                  f"the oracle on {nr} seeded alpha rows; bounded by resid")
+        result["davidson"] = dv
+        dctx.close()
+        del eig
+        torch.cuda.empty_cache()
+
     if args.serving_requests > 0:
         result["serving"] = serving_leg(T, W, args.serving_requests, args.serving_load)
+        if args.serving_requests < 512:
+            result["serving"]["note"] = (f"first {args.serving_requests} of the 512-request mix "
+                                         f"(the full mix does not fit this run's time; "
+                                         f"bench.py --serving-requests 512 runs it)")
     print(json.dumps(result), flush=True)
 
 

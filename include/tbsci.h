@@ -52,7 +52,10 @@ extern "C" {
 
 /* element type of C and sigma in tbsci_sigma */
 #define TBSCI_FP64 0
-#define TBSCI_FP32 1 /* FP32 inputs, FP32 arithmetic and accumulation      */
+#define TBSCI_FP32 1 /* FP32 inputs, outputs and arithmetic (MFMA and sweeps
+                        accumulate in FP32); the opposite-spin scatter adds
+                        into an FP64 copy of the output row where it fits in
+                        LDS, rounded to FP32 once per row                    */
 /* Davidson precision: FP32 sigma phase, then FP64 correction phase        */
 #define TBSCI_MIXED 2
 
@@ -116,10 +119,23 @@ int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int pr
  */
 int tbsci_diag(tbsci_ctx *ctx, double *diag_dev, void *stream);
 
+/* Davidson start vector */
+#define TBSCI_GUESS_DIAG 0 /* unit vector(s) on the smallest diagonal element          */
+#define TBSCI_GUESS_USER 1 /* the caller's vector guess_dev                             */
+/* Davidson vector storage */
+#define TBSCI_STORE_AUTO 0 /* FULL when it fits in 90% of the free device memory       */
+#define TBSCI_STORE_FULL 1 /* 2 n_max + 7 FP64 vectors (restart keeps two directions)  */
+#define TBSCI_STORE_LEAN 2 /* 2 n_max + 3 FP64 vectors (plain collapse restart)        */
+
 typedef struct {
     int n_max;                /* subspace size that triggers a restart, 2..16          */
-    int max_iter;             /* cap on sigma builds (both phases together)            */
+    int max_iter;             /* cap on sigma builds (both phases together, per sector)*/
     int precision;            /* TBSCI_FP64 or TBSCI_MIXED                              */
+    int guess_kind;           /* TBSCI_GUESS_DIAG or TBSCI_GUESS_USER                   */
+    int sector;               /* identical alpha/beta lists only: 0 = lowest state of
+                                 both spin-flip sectors, +1 = C^T = C only, -1 = C^T = -C
+                                 only (ignored for other spaces and for a user guess)   */
+    int storage;              /* TBSCI_STORE_AUTO, _FULL or _LEAN                        */
     double tol_resid;         /* stop when the FP64 residual norm <= tol_resid          */
     double tol_energy;        /* and |E_k - E_{k-1}| <= tol_energy (0 disables)         */
     double fp32_switch_resid; /* mixed: leave the FP32 phase below this residual        */
@@ -127,18 +143,25 @@ typedef struct {
 } tbsci_davidson_opts;
 
 typedef struct {
-    double energy;        /* lowest eigenvalue estimate (from an FP64 sigma)   */
-    double resid_norm;    /* ||H x - E x||_2 with an FP64 sigma               */
-    int iters;            /* sigma builds, both phases                         */
-    int iters_fp32;       /* sigma builds in FP32                              */
-    int iters_fp64;       /* sigma builds in FP64                              */
-    int converged;        /* 1 if the tolerances were met                       */
-    double t_total_s;     /* wall time of the solve                             */
-    double t_sigma_s;     /* part of it spent in sigma builds                   */
+    double energy;            /* lowest eigenvalue estimate (Ritz value, FP64 sigma)   */
+    double resid_norm;        /* ||H x - E x||_2 of that Ritz pair                     */
+    double energy_fp64_check; /* x^T H x / x^T x of the returned Ritz vector with a
+                                 fresh FP64 sigma build (certifies a mixed solve)       */
+    double energy_other;      /* lowest energy found in the other spin-flip sector
+                                 when both were solved, else NaN                        */
+    int iters;                /* sigma builds, all phases and sectors                  */
+    int iters_fp32;           /* sigma builds in FP32                                  */
+    int iters_fp64;           /* sigma builds in FP64 (energy checks included)         */
+    int converged;            /* 1 if the tolerances were met (in every sector solved) */
+    int sector;               /* +1: returned C has C^T = C, -1: C^T = -C, 0: no sector*/
+    int lean;                 /* 1 if the lean vector storage was used                 */
+    double t_total_s;         /* wall time of the solve                                */
+    double t_sigma_s;         /* part of it spent in sigma builds                      */
 } tbsci_davidson_info;
 
-/* Defaults: n_max 8, max_iter 200, FP64, tol_resid 1e-6, tol_energy 0,
- * fp32_switch_resid 1e-4, precond_floor 1e-8. */
+/* Defaults: n_max 8, max_iter 200, FP64, TBSCI_GUESS_DIAG, sector 0,
+ * TBSCI_STORE_AUTO, tol_resid 1e-6, tol_energy 0, fp32_switch_resid 1e-4,
+ * precond_floor 1e-8. */
 void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
 
 /*
@@ -150,30 +173,47 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
  * run in FP32 until the residual drops below fp32_switch_resid (or stops
  * falling), then the solver restarts from the Ritz vector with FP64 sigma
  * builds (Sec. III.A: a matrix-vector product in single precision with
- * everything else in double).
+ * everything else in double).  Every solve ends with one more FP64 sigma
+ * build of the Ritz vector, whose Rayleigh quotient is energy_fp64_check.
+ *
+ * Spin-flip sectors.  When the alpha and beta lists are the same strings in
+ * the same order and N_alpha = N_beta, H commutes with exchanging the two
+ * strings of every determinant, and every eigenvector can be taken with a
+ * symmetric (C^T = C: even total spin) or antisymmetric (C^T = -C: odd
+ * spin) CI matrix.  Rounding would slowly mix the two, so each solve is
+ * kept inside one sector (its corrections are (anti)symmetrised).  With
+ * sector 0 both sectors are solved one after the other and the lower state
+ * is returned (info.sector tells which; info.energy_other is the other
+ * one); with +1 or -1 only that sector.
  *
  *   opts      host, NULL for defaults
- *   guess_dev device double [l_alpha][l_beta] or NULL (unit vector on the
- *             smallest diagonal element, first in row-major order on ties;
- *             when the alpha and beta lists are the same strings in the
- *             same order and N_alpha = N_beta, H commutes with the spin
- *             flip C -> C^T and an open-shell start |I J> is replaced by
- *             (|I J> + |J I>)/sqrt 2: the solve then stays in the C = C^T
- *             sector, which holds the singlets, and returns its lowest
- *             state)
+ *   guess_dev device double [l_alpha][l_beta]: required with
+ *             TBSCI_GUESS_USER (no sector is imposed then), must be NULL
+ *             with TBSCI_GUESS_DIAG: the start is the unit vector on the
+ *             smallest diagonal element (first in row-major order on ties);
+ *             in a flip-symmetric space, (|I J> + |J I>)/sqrt 2 for an
+ *             open-shell |I J> in the symmetric sector, and
+ *             (|I J> - |J I>)/sqrt 2 on the open-shell determinant with the
+ *             smallest diagonal element in the antisymmetric one
  *   C_out_dev device double [l_alpha][l_beta] or NULL: receives the Ritz
- *             vector (unit norm, largest-magnitude entry positive)
+ *             vector (unit norm, largest-magnitude entry positive); during a
+ *             two-sector solve it also holds the first sector's vector
  *   info      host, required
  * Returns TBSCI_OK, or TBSCI_E_NOTCONV with info filled when the tolerance
- * was not met (TBSCI_E_INVAL for a zero guess).  Synchronous with respect
- * to the host, with one host synchronisation per iteration (the correction
- * and its sigma are built before the host sees that iteration's residual,
- * so a converged solve has built one sigma more than it used; info.iters
- * counts it).  Allocates its workspace ((2 n_max + 7) FP64 vectors, plus
- * two FP32 vectors for MIXED): the basis V and its images H V, the Ritz
- * vector and its image, the correction and its image, the previous Ritz
- * direction with its image, which the restart keeps next to the Ritz
- * vector, and the diagonal H_KK (Sec. II.C: computed once and stored).
+ * was not met (TBSCI_E_INVAL for a zero guess, an inconsistent guess_kind
+ * or an empty requested sector).  Synchronous with respect to the host,
+ * with one host synchronisation per iteration (the correction and its sigma
+ * are built before the host sees that iteration's residual, so a converged
+ * solve has built one sigma more than it used; info.iters counts it).
+ * Allocates its workspace: with TBSCI_STORE_FULL (2 n_max + 7) FP64
+ * vectors -- the basis V and its images H V, the Ritz vector and its image,
+ * the correction and its image, the previous Ritz direction with its image
+ * (the restart keeps it next to the Ritz vector) and the diagonal H_KK
+ * (Sec. II.C: computed once and stored); with TBSCI_STORE_LEAN
+ * (2 n_max + 3), the paper's count (Sec. III.C): the restart collapses to
+ * the Ritz vector, the image of the correction reuses a vector of the
+ * collapsed basis and H_KK is recomputed from per-string parts.  MIXED adds
+ * two FP32 vectors.  The sigma builds use the context's bounded workspace.
  */
 int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double *guess_dev,
                    double *C_out_dev, tbsci_davidson_info *info, void *stream);
@@ -200,12 +240,12 @@ int tbsci_sigma_batch(tbsci_ctx *const *ctxs, int n, const void *const *C_dev,
  * tbsci_davidson_batch: the lowest eigenvalue of every problem, solved in
  * lock step (one Davidson iteration of every unfinished problem per round,
  * one host synchronisation per round).  opts: NULL for defaults, else an
- * array of n.  infos[i] and status[i] (TBSCI_OK or
- * TBSCI_E_NOTCONV) receive problem i's result.  The start vector is that
- * of tbsci_davidson without a guess.  Eigenvectors are not
- * returned.  Each problem holds (2 n_max + 7) FP64 vectors, plus two FP32
- * vectors for TBSCI_MIXED, while it runs.  Returns TBSCI_OK when every
- * problem ran (whatever its own status), else an error code.
+ * array of n (guess_kind must be TBSCI_GUESS_DIAG).  infos[i] and
+ * status[i] (TBSCI_OK or TBSCI_E_NOTCONV) receive problem i's result; the
+ * start vectors and sectors are those of tbsci_davidson without a guess.
+ * Eigenvectors are not returned.  Each problem holds the vectors of its
+ * storage mode (as tbsci_davidson) while it runs.  Returns TBSCI_OK when
+ * every problem ran (whatever its own status), else an error code.
  */
 int tbsci_davidson_batch(tbsci_ctx *const *ctxs, int n, const tbsci_davidson_opts *opts,
                          tbsci_davidson_info *infos, int *status, void *stream);

@@ -24,8 +24,13 @@ Contents, each following the paper (arXiv 2503.10335):
 * ``davidson`` -- a plain Davidson eigensolver with collapse restart
   (Sec. II.B, Davidson matrix-vector products; Sec. III.C, restart with a
   bounded number of stored vectors).
-* ``fock_hamiltonian`` -- brute-force Jordan-Wigner Fock-space Hamiltonian
-  for tiny M, from the second-quantised operator, used only to pin the above.
+* ``lowest_by_flip_sector`` -- with identical alpha and beta lists, the
+  lowest eigenvalue of P H P among symmetric and among antisymmetric CI
+  matrices, and the lower of the two (the lowest eigenpair of Sec. II.B's
+  diagonalisation, split by the alpha/beta exchange symmetry of H).
+* ``fock_hamiltonian`` / ``fock_spin_squared`` -- brute-force Jordan-Wigner
+  Fock-space Hamiltonian and total spin for tiny M, from the second-quantised
+  operators, used only to pin the above.
 """
 from __future__ import annotations
 
@@ -333,6 +338,57 @@ def _fix_sign(x):
     return -x if x[k] < 0 else x
 
 
+# ------------------------------------------------------ spin-flip sectors
+
+def flip_sector_basis(l, tau):
+    """Orthonormal basis (columns) of the CI matrices C [l][l] with
+    C^T = tau C, as vectors of length l*l (row-major).  tau = +1: the unit
+    matrices on the diagonal and (e_ij + e_ji)/sqrt 2 for i < j; tau = -1:
+    (e_ij - e_ji)/sqrt 2 for i < j."""
+    cols = []
+    for i in range(l):
+        for j in range(i, l):
+            if i == j and tau < 0:
+                continue
+            v = np.zeros(l * l)
+            if i == j:
+                v[i * l + i] = 1.0
+            else:
+                v[i * l + j] = 1.0 / np.sqrt(2.0)
+                v[j * l + i] = tau / np.sqrt(2.0)
+            cols.append(v)
+    return np.array(cols).T.reshape(l * l, len(cols))
+
+
+def lowest_by_flip_sector(space, H=None):
+    """Lowest eigenvalue of P H P in each spin-flip sector and overall.
+
+    With the same strings in the same order for both spins (N_alpha =
+    N_beta), the spin-orbital H commutes with the exchange of the alpha and
+    beta strings of every determinant, so its eigenvectors can be taken as
+    CI matrices that are symmetric (C^T = C) or antisymmetric (C^T = -C).
+    Returns dict(sym=E+, anti=E- (None when l = 1), lowest=min, sector=+1 or
+    -1 of the lowest); for different lists only 'lowest' (sector 0).
+    Dense, for small spaces only."""
+    if H is None:
+        H = space.dense_h()
+    e_all = float(np.linalg.eigvalsh(H)[0])
+    same = (space.na == space.nb and space.la == space.lb
+            and np.array_equal(space.alpha, space.beta))
+    if not same:
+        return dict(sym=None, anti=None, lowest=e_all, sector=0)
+    l = space.la
+    out = {}
+    for tau, key in ((1, "sym"), (-1, "anti")):
+        Q = flip_sector_basis(l, tau)
+        out[key] = float(np.linalg.eigvalsh(Q.T @ H @ Q)[0]) if Q.shape[1] else None
+    lo = out["sym"] if out["anti"] is None or out["sym"] <= out["anti"] else out["anti"]
+    out["lowest"] = lo
+    out["sector"] = 1 if lo == out["sym"] else -1
+    out["lowest_all"] = e_all
+    return out
+
+
 # ------------------------------------------------------------ brute force
 
 def fock_hamiltonian(M, h, eri):
@@ -380,6 +436,26 @@ def fock_hamiltonian(M, h, eri):
                                 continue
                             H = H + (0.5 * v) * (Lp @ cre[so(r, t)] @ ann[so(u, t)] @ ann[so(q, s)])
     return H.tocsr()
+
+
+def fock_spin_squared(M):
+    """Total spin S^2 on the Fock space of M spatial orbitals (dimension
+    4^M, same basis and Jordan-Wigner signs as fock_hamiltonian), from its
+    textbook form S^2 = S_- S_+ + S_z (S_z + 1) with
+    S_+ = sum_p a+_{p alpha} a_{p beta}, S_- = S_+^T and
+    S_z = (1/2) sum_p (n_{p alpha} - n_{p beta}).  Returns a dense array."""
+    K = 2 * M
+    dim = 1 << K
+    ann = []
+    for X in range(K):
+        A = np.zeros((dim, dim))
+        for n in range(dim):
+            if (n >> X) & 1:
+                A[n ^ (1 << X), n] = -1.0 if bin(n & ((1 << X) - 1)).count("1") & 1 else 1.0
+        ann.append(A)
+    Sp = sum(ann[p].T @ ann[M + p] for p in range(M))
+    Sz = 0.5 * sum(ann[p].T @ ann[p] - ann[M + p].T @ ann[M + p] for p in range(M))
+    return Sp.T @ Sp + Sz @ (Sz + np.eye(dim))
 
 
 def fock_index(alpha_str, beta_str, M):

@@ -168,8 +168,8 @@ size_t spin_bytes(int M, int P, int n, int64_t l, int64_t n_s, int64_t n_d) {
 
 size_t fixed_bytes(int M, int P, int64_t l_alpha, int64_t l_beta) {
     const size_t M2 = (size_t)M * M, PP = (size_t)P * P;
-    const size_t nd = (size_t)(l_alpha * l_beta);
-    return page(8 * M2) + page(8 * M2 * M2) + page(8 * PP) + page(4 * PP) + page(16 * nd);
+    return page(8 * M2) + page(8 * M2 * M2) + page(8 * PP) + page(4 * PP) +
+           page(sigma_work_bytes(l_alpha, l_beta));
 }
 
 double binom(int n, int k) {

@@ -164,13 +164,15 @@ __global__ __launch_bounds__(kB) void gv_copy(const VDesc *__restrict__ d, int n
     TB_SLOT_LOOP(e, lb, t) e.o0[t] = e.in[t];
 }
 
-// per block: smallest H_KK and its first index
+// per block: smallest H_KK and its first index (in the antisymmetric
+// sector of a flip-symmetric space only open-shell determinants I != J)
 __global__ __launch_bounds__(kB) void gv_diag_min(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
     double best = 1e308;
     int64_t bi = -1;
     TB_SLOT_LOOP(e, lb, t) {
+        if (e.flip < 0 && t / e.lb == t % e.lb) continue;
         const double v = diag_at(e, t);
         if (v < best) {
             best = v;
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kB) void gv_diag_min(const VDesc *__restrict__ d, i
 
 // one block per slot: the start vector is the unit vector on the smallest
 // H_KK (first on ties); in a flip-symmetric space an open-shell |I J> is
-// paired with |J I>
+// paired with |J I>: (|I J> + flip |J I>)/sqrt 2 for sector flip = +1 or -1
 __global__ __launch_bounds__(kB) void gv_argmin_unit(const VDesc *__restrict__ d) {
     const VDesc e = d[blockIdx.x];
     double best = 1e308;
@@ -209,8 +211,8 @@ __global__ __launch_bounds__(kB) void gv_argmin_unit(const VDesc *__restrict__ d
         const int64_t ia = at / e.lb, ib = at - ia * e.lb;
         const int64_t at2 = e.flip ? ib * e.lb + ia : at;
         const double val = at2 == at ? 1.0 : 0.70710678118654752440;
+        e.o0[at2] = e.flip < 0 ? -val : val;
         e.o0[at] = val;
-        e.o0[at2] = val;
         e.scal[e.dst] = (double)at;
     }
 }
@@ -282,7 +284,7 @@ __device__ __forceinline__ void ritz_body(const VDesc &e, int64_t lb, double *ac
             av[i] = e.a[i][t];
             bv[i] = e.b[i][t];
         }
-        const double dk = e.in[t];
+        const double dk = e.in ? e.in[t] : diag_at(e, t);
         double xv = 0.0, wv = 0.0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -497,12 +499,12 @@ __global__ __launch_bounds__(kB) void gv_scale(const VDesc *__restrict__ d, int 
     }
 }
 
-// correction vectors of flip-symmetric slots: T = (T + T^T) / 2; d.nb is
-// the slot's tile-pair block count here
+// correction vectors of flip-symmetric slots: T = (T + flip T^T) / 2; d.nb
+// is the slot's tile-pair block count here
 __global__ __launch_bounds__(kB) void gv_flip_sym(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
-    flip_sym_block(lb, e.lb, e.o0);
+    flip_sym_block(lb, e.lb, (double)e.flip, e.o0);
 }
 
 __global__ __launch_bounds__(kB) void gv_to_f32(const VDesc *__restrict__ d, int nd) {
@@ -598,21 +600,44 @@ BatchEngine::~BatchEngine() {
     if (scal_host_) (void)hipHostFree(scal_host_);
 }
 
-size_t BatchEngine::slot_bytes(int64_t n, const tbsci_davidson_opts &o) {
+size_t BatchEngine::slot_bytes(int64_t n, const tbsci_davidson_opts &o, bool lean) {
     const size_t v = page(8 * (size_t)n);
-    size_t b = (2 * (size_t)(o.n_max + 3) + 1) * v + page(8 * (size_t)kSV * kNbMax);
+    // full: V and W pools of n_max + 3 and the stored diagonal; lean: pools
+    // of n_max + 2 and n_max + 1, the diagonal recomputed
+    const size_t nvec = lean ? 2 * (size_t)o.n_max + 3 : 2 * (size_t)(o.n_max + 3) + 1;
+    size_t b = nvec * v + page(8 * (size_t)kSV * kNbMax);
     if (o.precision == TBSCI_MIXED) b += 2 * page(4 * (size_t)n);
     return b;
 }
 
-BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o) {
+BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o, bool guess) {
+    const int64_t n = c->sp[0].l * c->sp[1].l;
+    bool lean = o.storage == TBSCI_STORE_LEAN;
+    if (o.storage == TBSCI_STORE_AUTO) {
+        size_t fr = 0, tot = 0;
+        TB_HIP(hipSetDevice(c->device));
+        TB_HIP(hipMemGetInfo(&fr, &tot));
+        lean = (double)slot_bytes(n, o, false) > 0.9 * (double)fr;
+    }
+    // sectors: a flip-symmetric space without a start vector is solved in
+    // the sector asked for, or in both (symmetric first)
+    int sector = 0, npass = 1;
+    if (c->flip && !guess) {
+        const bool anti_empty = c->sp[0].l < 2;
+        if (o.sector == -1 && anti_empty)
+            throw Error(TBSCI_E_INVAL, "the antisymmetric sector of a one-string space is empty");
+        sector = o.sector != 0 ? o.sector : 1;
+        npass = (o.sector == 0 && !anti_empty) ? 2 : 1;
+    }
     auto *s = new BatchSlot();
     try {
         s->c = c;
         s->o = o;
-        s->n = c->sp[0].l * c->sp[1].l;
+        s->n = n;
         s->nb = blocks_for_slot(s->n);
-        s->sym = c->flip;
+        s->sector = sector;
+        s->npass = npass;
+        s->lean = lean;
         auto get = [&](size_t bytes) {
             void *p = nullptr;
             TB_HIP(hipMalloc(&p, bytes));
@@ -620,11 +645,10 @@ BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o) {
             s->bytes += page(bytes);
             return p;
         };
-        for (int i = 0; i < o.n_max + 3; ++i) {
-            s->vfree.push_back((double *)get(8 * (size_t)s->n));
-            s->wfree.push_back((double *)get(8 * (size_t)s->n));
-        }
-        s->diag = (double *)get(8 * (size_t)s->n);
+        const int nv = lean ? o.n_max + 2 : o.n_max + 3, nw = lean ? o.n_max + 1 : o.n_max + 3;
+        for (int i = 0; i < nv; ++i) s->vfree.push_back((double *)get(8 * (size_t)s->n));
+        for (int i = 0; i < nw; ++i) s->wfree.push_back((double *)get(8 * (size_t)s->n));
+        if (!lean) s->diag = (double *)get(8 * (size_t)s->n);
         s->partial = (double *)get(8 * (size_t)kSV * kNbMax);
         if (o.precision == TBSCI_MIXED) {
             s->f32a = (float *)get(4 * (size_t)s->n);
@@ -651,9 +675,14 @@ void BatchEngine::add(BatchSlot *s) {
     free_rows_.pop_back();
     s->phase = BatchSlot::kStart;
     s->fp32 = s->o.precision == TBSCI_MIXED;
-    if (s->guess) s->sym = false;  // a caller's start vector picks its own sector
+    if (s->guess) {  // a caller's start vector picks its own sector
+        s->sector = 0;
+        s->npass = 1;
+    }
+    s->pass = 0;
     s->t0 = std::chrono::steady_clock::now();
     memset(&s->info, 0, sizeof(s->info));
+    s->info.lean = s->lean ? 1 : 0;
     act_.push_back(s);
 }
 
@@ -727,26 +756,35 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         return p;
     };
 
-    if (s.phase == BatchSlot::kFinish) {  // signed copy of the Ritz vector
-        VDesc m = base();
-        m.in = s.X;
-        S.ops[O_AMAX].push_back(m);
-        VDesc g = base();
-        g.in = s.X;
-        g.dst = sSign;
-        S.ops[O_AMAX_S].push_back(g);
-        VDesc o = base();
-        o.in = s.X;
-        o.o0 = s.out;
-        o.src = sSign;
-        S.ops[O_OUT].push_back(o);
+    if (s.phase == BatchSlot::kFinish) {
+        // the pass's Ritz vector x: its signed copy to the output when it is
+        // the lowest state so far, and a fresh FP64 sigma for x.x and x.Hx
+        if (s.write_out) {
+            VDesc m = base();
+            m.in = s.X;
+            S.ops[O_AMAX].push_back(m);
+            VDesc g = base();
+            g.in = s.X;
+            g.dst = sSign;
+            S.ops[O_AMAX_S].push_back(g);
+            VDesc o = base();
+            o.in = s.X;
+            o.o0 = s.out;
+            o.src = sSign;
+            S.ops[O_OUT].push_back(o);
+        }
+        P.W0 = take(s.wfree);
+        S.c64.push_back(s.c);
+        S.i64.push_back(s.X);
+        S.o64.push_back(P.W0);
+        dots(O_COL_D, {s.X, P.W0}, s.X, sCol);
         return;
     }
 
     const double *sig_in = nullptr;
     double *sig_out = nullptr;
     if (s.phase == BatchSlot::kStart || s.phase == BatchSlot::kHandover) {
-        if (s.phase == BatchSlot::kStart) {
+        if (s.phase == BatchSlot::kStart && s.diag && s.pass == 0) {
             VDesc dg = base();
             diag_fields(dg);
             dg.o0 = s.diag;
@@ -759,12 +797,13 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
             S.ops[O_FILL].push_back(f);
             VDesc m = base();
             diag_fields(m);
+            m.flip = s.sector;
             S.ops[O_DMIN].push_back(m);
             VDesc u = base();
             u.o0 = P.V0;
             u.dst = sArg;
             u.lb = s.c->sp[1].l;
-            u.flip = s.sym ? 1 : 0;
+            u.flip = s.sector;
             S.ops[O_AMIN].push_back(u);
         } else if (s.phase == BatchSlot::kStart) {
             P.V0 = take(s.vfree);
@@ -804,7 +843,7 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         P.Xn = take(s.vfree);
         P.WXn = take(s.wfree);
         P.T = take(s.vfree);
-        P.TW = take(s.wfree);
+        if (!(s.lean && k >= nm)) P.TW = take(s.wfree);  // else reused below
         P.sig32 = s.fp32;
         VDesc r = base();
         diag_fields(r);
@@ -822,17 +861,27 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         r.o2 = P.T;
         S.ops[O_RITZ].push_back(r);
         reduce(O_RITZ_R, 1, sR2);
-        if (s.sym) {  // keep the solve in the C = C^T sector
+        if (s.sector != 0) {  // keep the solve in its sector C^T = sector C
             VDesc y = base();
             const int64_t l = s.c->sp[1].l, nt = (l + 31) / 32;
             y.nb = (int32_t)(nt * nt);
             y.lb = l;
+            y.flip = s.sector;
             y.o0 = P.T;
             S.ops[O_SYM].push_back(y);
         }
 
         P.restart = k >= nm;
-        if (P.restart) {
+        if (P.restart && s.lean) {
+            // plain collapse to the Ritz vector; the image of the correction
+            // goes into a vector of the old W basis, which nothing reads after
+            // the Ritz kernel (the sigma runs after it in stream order)
+            dots(O_G0_D, {P.WXn}, P.Xn, sG);
+            P.Vb = {P.Xn};
+            P.Wb = {P.WXn};
+            P.TW = s.W.back();
+            P.tw_reused = true;
+        } else if (P.restart) {
             // keep x = V y and the part of the previous Ritz vector
             // orthogonal to it, z = yp - (yp.y) y (when there is room)
             std::vector<double> z(k);
@@ -1027,19 +1076,36 @@ bool BatchEngine::tick() {
     return true;
 }
 
-// The solve has ended with Ritz vector x: one more round writes the output
-// vector when one was asked for, else the slot is done now.
+// A pass has ended with Ritz vector x: one more round (kFinish) checks its
+// energy with a fresh FP64 sigma build and writes the output vector when x
+// is the lowest state so far.  x == nullptr: the solve ended with an error.
 void BatchEngine::finish(BatchSlot &s, double *x) {
-    if (s.fp32) s.info.converged = 0;  // never certified by an FP64 sigma
-    if (s.status == TBSCI_PENDING) s.status = s.info.converged ? TBSCI_OK : TBSCI_E_NOTCONV;
-    s.info.energy = s.theta;
-    s.info.resid_norm = s.rn;
-    if (s.out && x && s.phase != BatchSlot::kFinish) {
-        s.X = x;
-        s.phase = BatchSlot::kFinish;
+    if (s.fp32) s.pass_conv = false;  // never certified by an FP64 sigma
+    if (!x) {
+        complete(s);
         return;
     }
-    if (x) s.vfree.push_back(x);
+    s.X = x;
+    s.write_out = s.out && (!s.best.valid || s.theta < s.best.e);
+    s.phase = BatchSlot::kFinish;
+}
+
+// the solve's result from its passes (the lowest state found)
+void BatchEngine::complete(BatchSlot &s) {
+    if (s.best.valid) {
+        s.info.energy = s.best.e;
+        s.info.resid_norm = s.best.rn;
+        s.info.energy_fp64_check = s.best.echk;
+        s.info.sector = s.best.sector;
+    } else {
+        s.info.energy = s.theta;
+        s.info.resid_norm = s.rn;
+        s.info.energy_fp64_check = std::nan("");
+        s.info.sector = s.sector;
+    }
+    s.info.energy_other = s.have_other ? s.e_other : std::nan("");
+    s.info.converged = (s.best.valid && s.all_conv) ? 1 : 0;
+    if (s.status == TBSCI_PENDING) s.status = s.info.converged ? TBSCI_OK : TBSCI_E_NOTCONV;
     s.phase = BatchSlot::kDone;
     s.info.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - s.t0).count();
 }
@@ -1048,9 +1114,45 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     auto &P = s.p;
     const int nm = s.o.n_max;
     if (s.phase == BatchSlot::kFinish) {
-        double *x = s.X;
+        s.info.iters++;
+        s.info.iters_fp64++;
+        s.info.t_sigma_s += t_sig;
+        BatchSlot::PassResult cur;
+        cur.valid = true;
+        cur.e = s.theta;
+        cur.rn = s.rn;
+        cur.echk = r[sCol] > 0.0 ? r[sCol + 1] / r[sCol] : std::nan("");
+        cur.sector = s.sector;
+        s.all_conv = s.all_conv && s.pass_conv;
+        if (!s.best.valid || cur.e < s.best.e) {
+            if (s.best.valid) {
+                s.e_other = s.best.e;
+                s.have_other = true;
+            }
+            s.best = cur;
+        } else {
+            s.e_other = cur.e;
+            s.have_other = true;
+        }
+        s.vfree.push_back(s.X);
         s.X = nullptr;
-        finish(s, x);
+        s.wfree.push_back(P.W0);
+        if (s.pass + 1 < s.npass) {  // the antisymmetric sector, from its own start
+            s.pass++;
+            s.sector = -1;
+            s.phase = BatchSlot::kStart;
+            s.fp32 = s.o.precision == TBSCI_MIXED;
+            s.k = 0;
+            s.V.clear();
+            s.W.clear();
+            s.yprev.clear();
+            s.theta = s.theta_prev = 0.0;
+            s.rn = s.best_rn = 1e300;
+            s.since_best = 0;
+            s.pass_conv = false;
+            return;
+        }
+        complete(s);
         return;
     }
     s.info.iters++;
@@ -1104,7 +1206,7 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
         s.W.clear();
         release_w(P.WXn);
         release_v(P.T);
-        release_w(P.TW);
+        if (!P.tw_reused) release_w(P.TW);  // else it was one of s.W
         release_v(P.XP);
         release_w(P.WXP);
     };
@@ -1127,7 +1229,7 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
                    s.info.iters >= s.o.max_iter / 2 || dropped;
     } else if (s.rn <= s.o.tol_resid &&
                (s.o.tol_energy <= 0.0 || std::fabs(s.theta - s.theta_prev) <= s.o.tol_energy)) {
-        s.info.converged = 1;
+        s.pass_conv = true;
         drop_all_but_x();
         finish(s, P.Xn);
         return;
@@ -1148,7 +1250,8 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     std::vector<int> pos;
     if (P.restart) {
         for (double *p : s.V) release_v(p);
-        for (double *p : s.W) release_w(p);
+        for (double *p : s.W)
+            if (!(P.tw_reused && p == P.TW)) release_w(p);
         const bool two = P.took_xp && std::sqrt(std::max(r[sN2], 0.0)) > 1e-8;
         std::fill(s.G.begin(), s.G.end(), 0.0);
         if (two) {
@@ -1186,7 +1289,7 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
 int solve_one(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *out,
               tbsci_davidson_info &info, hipStream_t st, const std::atomic<bool> *abort) {
     reserve_sigma_workspace(c);
-    BatchSlot *s = BatchEngine::make_slot(&c, o);
+    BatchSlot *s = BatchEngine::make_slot(&c, o, guess != nullptr);
     s->guess = guess;
     s->out = out;
     int rc = TBSCI_OK;
@@ -1237,6 +1340,9 @@ int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double
         tbsci_davidson_default_opts(&o);
         if (opts) o = *opts;
         check_opts(o);
+        if ((o.guess_kind == TBSCI_GUESS_USER) != (guess_dev != nullptr))
+            throw Error(TBSCI_E_INVAL, "guess_dev must be given exactly when guess_kind is "
+                                       "TBSCI_GUESS_USER");
         if (guess_dev) check_dev(guess_dev, c->device, "guess");
         if (C_out_dev) check_dev(C_out_dev, c->device, "C_out");
         tbsci_davidson_info tmp;
@@ -1297,6 +1403,8 @@ int tbsci_davidson_batch(tbsci_ctx *const *ctxs, int n, const tbsci_davidson_opt
             else
                 tbsci_davidson_default_opts(&os[i]);
             check_opts(os[i]);
+            if (os[i].guess_kind != TBSCI_GUESS_DIAG)
+                throw Error(TBSCI_E_INVAL, "batched solves take no start vector");
         }
         TB_HIP(hipSetDevice(cs[0]->device));
         hipStream_t st = (hipStream_t)stream;

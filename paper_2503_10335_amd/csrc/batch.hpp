@@ -37,7 +37,11 @@ struct BatchSlot {
     tbsci_davidson_opts o{};
     const double *guess = nullptr;  // optional start vector (device)
     double *out = nullptr;          // optional eigenvector output (device)
-    bool sym = false;               // keep the solve in the C = C^T sector
+    // spin-flip sector of the current pass: +1 (C^T = C), -1 (C^T = -C) or
+    // 0 (none imposed); a two-sector solve runs pass 0 in +1, pass 1 in -1
+    int sector = 0;
+    int npass = 1, pass = 0;
+    bool lean = false;  // 2 n_max + 3 vectors: collapse restart, no stored diagonal
     int64_t n = 0;
     int nb = 1;    // blocks of this slot in grid-stride launches
     int row = -1;  // row of the scalar area while active
@@ -51,8 +55,23 @@ struct BatchSlot {
     double *partial = nullptr;
     size_t bytes = 0;  // device bytes of the above (page-rounded)
     // host state
+    //  kStart    start vector of a pass and its sigma
+    //  kHandover mixed precision: FP64 restart from the FP32 Ritz vector
+    //  kIter     one Davidson iteration
+    //  kFinish   FP64 sigma of the pass's Ritz vector (energy check), and its
+    //            signed copy to the output when it is the lowest so far
     enum { kStart, kHandover, kIter, kFinish, kDone } phase = kStart;
     bool fp32 = false;
+    bool pass_conv = false;  // the current pass met the tolerances
+    bool write_out = false;  // the finish round writes the output vector
+    bool all_conv = true;    // every finished pass met the tolerances
+    struct PassResult {
+        bool valid = false;
+        double e = 0.0, rn = 0.0, echk = 0.0;
+        int sector = 0;
+    } best;
+    double e_other = 0.0;
+    bool have_other = false;
     int k = 0;
     std::vector<double> G, y, yprev;
     double theta = 0.0, theta_prev = 0.0, rn = 1e300, best_rn = 1e300;
@@ -67,6 +86,7 @@ struct BatchSlot {
         bool sig32 = false, restart = false, took_xp = false;
         double *V0 = nullptr, *W0 = nullptr;  // start / hand-over
         double *Xn = nullptr, *WXn = nullptr, *T = nullptr, *TW = nullptr;
+        bool tw_reused = false;  // lean restart: TW is a vector of the old W basis
         double *XP = nullptr, *WXP = nullptr;
         std::vector<double *> Vb, Wb;  // basis the new vector joins
     } p;
@@ -79,10 +99,16 @@ class BatchEngine {
     BatchEngine(const BatchEngine &) = delete;
     BatchEngine &operator=(const BatchEngine &) = delete;
 
-    // device bytes of a slot's solver state for n determinants
-    static size_t slot_bytes(int64_t n, const tbsci_davidson_opts &o);
-    // allocate a slot for context c (any thread; allocation only)
-    static BatchSlot *make_slot(Ctx *c, const tbsci_davidson_opts &o);
+    // device bytes of a slot's solver state for n determinants (lean or
+    // full storage; without `lean`, the mode the options ask for, full for
+    // TBSCI_STORE_AUTO: an upper bound)
+    static size_t slot_bytes(int64_t n, const tbsci_davidson_opts &o, bool lean);
+    static size_t slot_bytes(int64_t n, const tbsci_davidson_opts &o) {
+        return slot_bytes(n, o, o.storage == TBSCI_STORE_LEAN);
+    }
+    // allocate a slot for context c (any thread; allocation only); guess:
+    // whether a start vector will be given (no sector is imposed then)
+    static BatchSlot *make_slot(Ctx *c, const tbsci_davidson_opts &o, bool guess = false);
     // free a slot's buffers (not its context); any thread, slot not active
     static void free_slot(BatchSlot *s);
 
@@ -105,6 +131,7 @@ class BatchEngine {
     void plan(BatchSlot &s, Stage &S);
     void commit(BatchSlot &s, const double *r, double t_sig);
     void finish(BatchSlot &s, double *keep);
+    void complete(BatchSlot &s);
 
     int device_;
     hipStream_t st_;

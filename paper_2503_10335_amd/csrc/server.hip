@@ -382,6 +382,8 @@ int tbsci_submit(tbsci_server *srv, int M, int n_alpha, int n_beta, const double
         else
             tbsci_davidson_default_opts(&r->o);
         check_opts(r->o);
+        if (r->o.guess_kind != TBSCI_GUESS_DIAG)
+            throw Error(TBSCI_E_INVAL, "served solves take no start vector");
         r->M = M;
         r->na = n_alpha;
         r->nb = n_beta;

@@ -793,10 +793,10 @@ __global__ __launch_bounds__(kSlabBlock) void g_ab_slab(const SlabDesc *__restri
 
 // ---------------------------------------------------------------- driver
 
-template <typename T>
-T *workspace(Ctx &c, int which) {
-    const size_t nd = (size_t)(c.sp[0].l * c.sp[1].l);
-    const size_t need = 2 * nd * sizeof(double);
+// the context's beta-sweep workspace (sigma_work_bytes), allocated on
+// first use
+void *ctx_workspace(Ctx &c) {
+    const size_t need = sigma_work_bytes(c.sp[0].l, c.sp[1].l);
     if (c.work_bytes < need) {
         if (c.work) TB_HIP(hipFree(c.work));
         c.work = nullptr;
@@ -804,7 +804,24 @@ T *workspace(Ctx &c, int which) {
         TB_HIP(hipMalloc(&c.work, need));
         c.work_bytes = need;
     }
-    return (T *)c.work + which * nd;
+    return c.work;
+}
+
+// o[i] = 0 for i < n (a kernel rather than a memset node, so that the
+// sigma launches can be captured into a graph)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero(int64_t n, T *__restrict__ o) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        o[i] = T(0);
+}
+
+template <typename T>
+void launch_zero(int64_t n, T *o, hipStream_t st) {
+    if (n <= 0) return;
+    const int64_t g = std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+    k_zero<T><<<(unsigned)g, kBlock, 0, st>>>(n, o);
+    TB_HIP(hipGetLastError());
 }
 
 // Y (+)= A_s X.  With more than one source chunk, one pass per chunk (the
@@ -972,24 +989,29 @@ __global__ __launch_bounds__(kBlock) void k_ab_direct(int64_t lb, int64_t ncb, i
     S[I * lb + Ip] += acc;
 }
 
+// sigma with the beta sweep in blocks of rb alpha rows; work holds
+// 2 l_beta rb elements of type T (C^T and the sweep result of a block)
 template <typename T>
-void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms) {
+void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work, int64_t rb) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     const int64_t la = A.l, lb = B.l;
     const int prec = sizeof(T) == 8 ? TBSCI_FP64 : TBSCI_FP32;
-    T *Ct = workspace<T>(c, 0);
-    T *St = workspace<T>(c, 1);
 
     timing_mark(c, 0, prec, st);
     if (terms & 1)
         launch_row_sweep<T>(A, lb, C, S, false, st);  // sigma = A_a C
     else
-        TB_HIP(hipMemsetAsync(S, 0, (size_t)(la * lb) * sizeof(T), st));
+        launch_zero<T>(la * lb, S, st);
     timing_mark(c, 1, prec, st);
     if (terms & 2) {
-        launch_transpose<T, false>(la, lb, C, Ct, st);  // sigma += (A_b C^T)^T
-        launch_row_sweep<T>(B, la, Ct, St, false, st);
-        launch_transpose<T, true>(lb, la, St, S, st);
+        // sigma[r0 : r0 + nr] += (A_b C[r0 : r0 + nr]^T)^T, block by block
+        T *Ct = (T *)work, *St = (T *)work + (size_t)lb * rb;
+        for (int64_t r0 = 0; r0 < la; r0 += rb) {
+            const int64_t nr = std::min(rb, la - r0);
+            launch_transpose<T, false>(nr, lb, C + r0 * lb, Ct, st);
+            launch_row_sweep<T>(B, nr, Ct, St, false, st);
+            launch_transpose<T, true>(lb, nr, St, S + r0 * lb, st);
+        }
     }
     timing_mark(c, 2, prec, st);
     if (!(terms & 4)) {
@@ -1052,7 +1074,7 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
     for (int i = 0; i < n; ++i) {
         Ctx &c = *ctx[i];
         const Spin &A = c.sp[0], &B = c.sp[1];
-        T *Ct = workspace<T>(c, 0), *St = workspace<T>(c, 1);
+        T *Ct = (T *)ctx_workspace(c), *St = Ct + (size_t)A.l * B.l;
         sweep(sa, bsa, A, B.l, C[i], S[i]);
         trans(t1, bt1, A.l, B.l, C[i], Ct);
         sweep(sb, bsb, B, A.l, Ct, St);
@@ -1108,17 +1130,35 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
 
 void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, int n,
                         int precision, TableArena &ar, hipStream_t st) {
-    if (n == 1) {  // a group of one: the kernels of a single sigma build
-        launch_sigma(*ctx[0], C[0], S[0], precision, st);
-        return;
+    // problems whose beta sweep runs in more than one block take their own
+    // launches; the others share them
+    std::vector<Ctx *> gc;
+    std::vector<const void *> gC;
+    std::vector<void *> gS;
+    for (int i = 0; i < n; ++i) {
+        const int64_t la = ctx[i]->sp[0].l, lb = ctx[i]->sp[1].l;
+        if (n == 1 || beta_block_rows(la, lb, kWorkCap) < la) {
+            launch_sigma(*ctx[i], C[i], S[i], precision, st);
+        } else {
+            gc.push_back(ctx[i]);
+            gC.push_back(C[i]);
+            gS.push_back(S[i]);
+        }
     }
-    if (precision == TBSCI_FP64)
-        sigma_group_impl<double>(ctx, (const double *const *)C, (double *const *)S, n, ar, st);
-    else
-        sigma_group_impl<float>(ctx, (const float *const *)C, (float *const *)S, n, ar, st);
+    const int m = (int)gc.size();
+    if (m == 1) {
+        launch_sigma(*gc[0], gC[0], gS[0], precision, st);
+    } else if (m > 1) {
+        if (precision == TBSCI_FP64)
+            sigma_group_impl<double>(gc.data(), (const double *const *)gC.data(),
+                                     (double *const *)gS.data(), m, ar, st);
+        else
+            sigma_group_impl<float>(gc.data(), (const float *const *)gC.data(),
+                                    (float *const *)gS.data(), m, ar, st);
+    }
 }
 
-void reserve_sigma_workspace(Ctx &c) { (void)workspace<double>(c, 0); }
+void reserve_sigma_workspace(Ctx &c) { (void)ctx_workspace(c); }
 
 void timing_mark(Ctx &c, int index, int precision, hipStream_t st) {
     if (!c.timing) return;
@@ -1138,11 +1178,24 @@ void timing_clear(Ctx &c) {
     c.timed.clear();
 }
 
-void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms) {
+void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
+                     void *work, size_t work_bytes) {
+    const int64_t la = c.sp[0].l, lb = c.sp[1].l;
+    int64_t rb = la;
+    if (terms & 2) {
+        rb = beta_block_rows(la, lb, work_bytes);
+        if (rb < 1)
+            throw Error(TBSCI_E_INVAL, "the workspace cannot hold the beta sweep of one alpha row");
+    }
     if (precision == TBSCI_FP64)
-        sigma_impl<double>(c, (const double *)C, (double *)S, st, terms);
+        sigma_impl<double>(c, (const double *)C, (double *)S, st, terms, work, rb);
     else
-        sigma_impl<float>(c, (const float *)C, (float *)S, st, terms);
+        sigma_impl<float>(c, (const float *)C, (float *)S, st, terms, work, rb);
+}
+
+void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms) {
+    void *w = ctx_workspace(c);
+    launch_sigma_ws(c, C, S, precision, st, terms, w, c.work_bytes);
 }
 
 // Floating-point operations one launch of kernel `kernel` executes: for the

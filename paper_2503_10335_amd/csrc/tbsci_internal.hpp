@@ -77,6 +77,26 @@ struct Spin {
     int32_t *g_off = nullptr;
 };
 
+// The beta sweep runs on C^T: for a block of alpha rows it transposes the
+// block, sweeps the transposed rows with A_beta and adds the transposed
+// result back into sigma.  Its workspace holds C^T and the sweep result of
+// one block, 2 l_beta rows FP64 elements; blocks take every row when that
+// fits in `cap` bytes, else the most rows that fit, rounded down to whole
+// column tiles of the sweep on every XCD (multiples of 2048, or of 256 for
+// short blocks).  0 when not even one row fits.
+constexpr size_t kWorkCap = size_t(2) << 30;
+inline int64_t beta_block_rows(int64_t la, int64_t lb, size_t cap) {
+    const size_t per_row = 2 * (size_t)lb * sizeof(double);
+    const int64_t fit = (int64_t)(cap / per_row);
+    if (fit >= la) return la;
+    if (fit >= 2048) return fit / 2048 * 2048;
+    if (fit >= 256) return fit / 256 * 256;
+    return fit;
+}
+inline size_t sigma_work_bytes(int64_t la, int64_t lb) {
+    return 2 * (size_t)lb * (size_t)beta_block_rows(la, lb, kWorkCap) * sizeof(double);
+}
+
 // Sweep source chunk: the gathered rows of one chunk, 128 columns wide in
 // FP64, fill 3 MB of an XCD's 4 MB L2
 constexpr int64_t kSweepChunk = 3072;
@@ -98,14 +118,16 @@ struct Ctx {
     int M = 0, P = 0, device = 0;
     // alpha and beta lists are the same strings in the same order with
     // N_alpha = N_beta: H commutes with the spin flip C -> C^T (up to the
-    // sign (-1)^N), and the solvers start in the C = C^T sector
+    // sign (-1)^N), and the solvers work in the C^T = C and C^T = -C
+    // sectors separately
     bool flip = false;
     double *h = nullptr;     // [M][M]
     double *eri = nullptr;   // [M^4]
     double *V64 = nullptr;   // folded [P][P]: V[pair(p,q)][pair(r,s)] = (pq|rs)
     float *V32 = nullptr;
     Spin sp[2];
-    // sigma workspace (grown on demand)
+    // sigma workspace of the beta sweep (allocated on first use; see
+    // beta_block_rows)
     void *work = nullptr;
     size_t work_bytes = 0;
     // per-kernel event timing (measurement only)
@@ -214,7 +236,12 @@ void launch_lookup(const Spin &s, const uint64_t *q, int64_t n, int32_t *out, hi
 void launch_full_diag(const Ctx &c, double *out, hipStream_t st);
 
 // ---- launchers (sigma_kernels.hip)
+// sigma with the context's workspace (allocated on first use)
 void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms = 7);
+// sigma with a caller-provided workspace of work_bytes bytes (the beta
+// sweep runs in blocks that fit; throws TBSCI_E_INVAL when one row does not)
+void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
+                     void *work, size_t work_bytes);
 double executed_flops(Ctx &c, int kernel, int precision);
 // sigma of n problems in shared launches (one per kernel type, the
 // opposite-spin term one per group of equal tile shape); C[i], S[i] are
@@ -225,11 +252,12 @@ void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, i
 void reserve_sigma_workspace(Ctx &c);
 
 // ---- davidson.hip
-// T = (T + T^T) / 2 in place for a square l x l row-major matrix, one
-// 256-thread block per 32 x 32 tile pair (bi <= bj; blocks with bi > bj
-// return); used on correction vectors to keep a flip-symmetric solve in
-// the C = C^T sector
-__device__ __forceinline__ void flip_sym_block(int64_t b, int64_t l, double *__restrict__ T) {
+// T = (T + tau T^T) / 2 in place for a square l x l row-major matrix
+// (tau = +1 or -1), one 256-thread block per 32 x 32 tile pair (bi <= bj;
+// blocks with bi > bj return); used on correction vectors to keep a
+// flip-symmetric solve in the C^T = tau C sector
+__device__ __forceinline__ void flip_sym_block(int64_t b, int64_t l, double tau,
+                                               double *__restrict__ T) {
     __shared__ double A[32][33], B[32][33];
     const int64_t nt = (l + 31) / 32, bi = b / nt, bj = b - bi * nt;
     if (bi > bj) return;
@@ -243,9 +271,9 @@ __device__ __forceinline__ void flip_sym_block(int64_t b, int64_t l, double *__r
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int64_t i = bi * 32 + r, j = bj * 32 + tx;
-        if (i < l && j < l) T[i * l + j] = 0.5 * (A[r][tx] + B[tx][r]);
+        if (i < l && j < l) T[i * l + j] = 0.5 * (A[r][tx] + tau * B[tx][r]);
         const int64_t i2 = bj * 32 + r, j2 = bi * 32 + tx;
-        if (i2 < l && j2 < l) T[i2 * l + j2] = 0.5 * (B[r][tx] + A[tx][r]);
+        if (i2 < l && j2 < l) T[i2 * l + j2] = 0.5 * (B[r][tx] + tau * A[tx][r]);
     }
 }
 

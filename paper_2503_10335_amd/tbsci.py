@@ -17,8 +17,7 @@ import numpy as np
 import torch  # loads the HIP runtime the library binds to (same soname)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# TBSCI_LIB may point at another build of the same library (same ABI)
-LIB_PATH = os.environ.get("TBSCI_LIB") or os.path.join(_HERE, "libtbsci.so")
+LIB_PATH = os.path.join(_HERE, "libtbsci.so")
 
 TBSCI_OK = 0
 TBSCI_PENDING = 1
@@ -39,8 +38,16 @@ class TbsciError(RuntimeError):
         self.code = code
 
 
+TBSCI_GUESS_DIAG = 0
+TBSCI_GUESS_USER = 1
+TBSCI_STORE_AUTO = 0
+TBSCI_STORE_FULL = 1
+TBSCI_STORE_LEAN = 2
+
+
 class DavidsonOpts(ctypes.Structure):
     _fields_ = [("n_max", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
+                ("guess_kind", ctypes.c_int), ("sector", ctypes.c_int), ("storage", ctypes.c_int),
                 ("tol_resid", ctypes.c_double), ("tol_energy", ctypes.c_double),
                 ("fp32_switch_resid", ctypes.c_double), ("precond_floor", ctypes.c_double)]
 
@@ -59,9 +66,10 @@ class ServerInfo(ctypes.Structure):
 
 class DavidsonInfo(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("resid_norm", ctypes.c_double),
+                ("energy_fp64_check", ctypes.c_double), ("energy_other", ctypes.c_double),
                 ("iters", ctypes.c_int), ("iters_fp32", ctypes.c_int), ("iters_fp64", ctypes.c_int),
-                ("converged", ctypes.c_int), ("t_total_s", ctypes.c_double),
-                ("t_sigma_s", ctypes.c_double)]
+                ("converged", ctypes.c_int), ("sector", ctypes.c_int), ("lean", ctypes.c_int),
+                ("t_total_s", ctypes.c_double), ("t_sigma_s", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -324,9 +332,11 @@ def tbsci_server_stats(srv):
 
 
 def make_opts(n_max=8, max_iter=200, precision=TBSCI_FP64, tol_resid=1e-6, tol_energy=0.0,
-              fp32_switch_resid=1e-4, precond_floor=1e-8):
+              fp32_switch_resid=1e-4, precond_floor=1e-8, sector=0, storage=TBSCI_STORE_AUTO,
+              guess_kind=TBSCI_GUESS_DIAG):
     o = tbsci_davidson_default_opts()
     o.n_max, o.max_iter, o.precision = n_max, max_iter, precision
+    o.guess_kind, o.sector, o.storage = guess_kind, sector, storage
     o.tol_resid, o.tol_energy = tol_resid, tol_energy
     o.fp32_switch_resid, o.precond_floor = fp32_switch_resid, precond_floor
     return o
@@ -432,9 +442,10 @@ class Context:
 
     def davidson(self, n_max=8, max_iter=200, precision=TBSCI_FP64, tol_resid=1e-6,
                  tol_energy=0.0, fp32_switch_resid=1e-4, precond_floor=1e-8, guess=None,
-                 want_vector=True, stream=None):
+                 want_vector=True, sector=0, storage=TBSCI_STORE_AUTO, stream=None):
         o = make_opts(n_max, max_iter, precision, tol_resid, tol_energy, fp32_switch_resid,
-                      precond_floor)
+                      precond_floor, sector, storage,
+                      TBSCI_GUESS_USER if guess is not None else TBSCI_GUESS_DIAG)
         if guess is not None and (guess.dtype != torch.float64 or guess.numel() != self.n_det):
             raise ValueError("guess must be an FP64 device tensor of n_det elements")
         X = torch.empty((self.l_alpha, self.l_beta), dtype=torch.float64,

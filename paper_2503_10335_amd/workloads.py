@@ -160,6 +160,21 @@ def random_vector(n_alpha_rows: int, n_beta_cols: int, seed: int = 7) -> np.ndar
     return C
 
 
+def random_vector_device(n_alpha_rows: int, n_beta_cols: int, seed: int = 7,
+                         device="cuda:0", dtype=None):
+    """N(0,1) CI matrix [l_alpha][l_beta] drawn on the device by torch's
+    generator of that device (seeded), normalised to unit 2-norm: the input
+    of the full-size sigma timings, where a host draw and copy of tens of
+    GB would dominate the run."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    C = torch.randn((n_alpha_rows, n_beta_cols), generator=g, device=device,
+                    dtype=dtype or torch.float64)
+    C /= torch.linalg.vector_norm(C)
+    return C
+
+
 def serving_mix(n_requests: int = 512, seed: int = 5005, rate_per_s: float = 10.0):
     """Request stream: M uniform in {10,12,14,16}, N = M/2, string count
     log-uniform in [500, 4000] clamped to C(M, N), Poisson arrival times.

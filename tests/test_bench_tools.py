@@ -42,13 +42,41 @@ def test_summarize_traffic_and_hash_gate(tmp_path, monkeypatch):
                     ["cmd"])
     text = out.read_text()
     expect = 2000 * 1024 * 2 + 500 * 1024 * 1  # KiB per dispatch x factor, fetch + write
-    assert f"traffic opposite_spin fp64 {expect}" in text
+    assert f"traffic opposite_spin fp64 {expect} k_ab_slab<double,20>" in text
     assert "fetch_factor 2.0000 write_factor 1.0000" in text
     monkeypatch.setattr(bench, "PROFILE", str(out))
-    assert bench.measured_traffic("opposite_spin", "fp64") == expect
-    assert bench.measured_traffic("opposite_spin", "fp32") is None
+    assert bench.measured_traffic("opposite_spin", "fp64") == (expect, "k_ab_slab<double,20>")
+    assert bench.measured_traffic("opposite_spin", "fp32") == (None, None)
     monkeypatch.setattr(bench, "source_hash", lambda: "changed")
-    assert bench.measured_traffic("opposite_spin", "fp64") is None
+    assert bench.measured_traffic("opposite_spin", "fp64") == (None, None)
+
+
+def test_summarize_title_and_ambiguous_kernels(tmp_path):
+    """The summary header is the profiled workload's title, and a run in
+    which two kernels serve the same term and precision is refused (its
+    traffic could not be attributed)."""
+    import pytest
+    trace = tmp_path / "trace"
+    trace.mkdir()
+    K2 = "void tbsci::(anonymous namespace)::k_ab_slabg<double, 24, 2>(long, int)"
+    _write(trace / "x_kernel_stats.csv",
+           ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"],
+           [[KNAME, 1, 3000000, 3000000, 50.0, 3000000, 3000000]])
+    _counters(str(tmp_path / "fetch"), "FETCH_SIZE",
+              [(COPY, 131072.0, 5), (KNAME, 1000.0, 7)])
+    _counters(str(tmp_path / "write"), "WRITE_SIZE",
+              [(COPY, 262144.0, 5), (KNAME, 500.0, 7)])
+    out = tmp_path / "s.txt"
+    bench.summarize(str(trace), str(tmp_path / "fetch"), str(tmp_path / "write"), str(out),
+                    ["cmd"], "my workload title")
+    assert out.read_text().startswith("# rocprofv3 summary: my workload title")
+    _counters(str(tmp_path / "fetch2"), "FETCH_SIZE",
+              [(COPY, 131072.0, 5), (KNAME, 1000.0, 7), (K2, 10.0, 7)])
+    _counters(str(tmp_path / "write2"), "WRITE_SIZE",
+              [(COPY, 262144.0, 5), (KNAME, 500.0, 7), (K2, 10.0, 7)])
+    with pytest.raises(SystemExit):
+        bench.summarize(str(trace), str(tmp_path / "fetch2"), str(tmp_path / "write2"),
+                        str(tmp_path / "s2.txt"), ["cmd"])
 
 
 def test_summarize_counters_means(tmp_path):

@@ -5,6 +5,7 @@ match bit for bit; FP64 sigma to 1e-12 relative (norm-wise and max-wise);
 FP64 energies to 1e-8 Eh; FP32 sigma to 2e-5 relative (FP32 rounding of
 sums of a few thousand terms).
 """
+import ctypes
 import math
 
 import numpy as np
@@ -243,13 +244,106 @@ def test_davidson_guess_and_vector(env):
     assert np.linalg.norm(sp.sigma(x).ravel() - info["energy"] * x) < 5e-9
     # warm start (scaled, to exercise the normalisation of the guess)
     info2, X2 = ctx.davidson(tol_resid=1e-9, n_max=8, guess=3.0 * X)
-    assert info2["status"] == 0 and info2["iters"] <= 3
+    # at most two iterations and the final FP64 energy check
+    assert info2["status"] == 0 and info2["iters"] <= 4 and info2["sector"] == 0
     assert abs(info2["energy"] - info["energy"]) < 1e-10
     assert np.abs(X2.cpu().numpy() - X.cpu().numpy()).max() < 1e-8
     with pytest.raises(T.TbsciError) as ei:
         ctx.davidson(guess=torch.zeros_like(X))
     assert ei.value.code == T.TBSCI_E_INVAL and "zero" in str(ei.value)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_davidson_both_flip_sectors(env, prec):
+    """Identical lists whose lowest state is antisymmetric (M = 8, N = 4,
+    every string, integral seed 100): the default solve returns the lowest
+    eigenvalue of the oracle's dense P H P over both sectors, reports sector
+    -1, the symmetric sector's lowest as energy_other, and an antisymmetric
+    eigenvector; a solve restricted to one sector returns that sector's
+    lowest state; lean storage gives the same energies."""
+    T, O, torch = env
+    p = W.make_problem("anti_gs", 8, 4, None, 100)
+    ref = O.lowest_by_flip_sector(O.Space.of(p))
+    assert ref["sector"] == -1
+    pr = T.TBSCI_FP64 if prec == "fp64" else T.TBSCI_MIXED
+    tol_e = 1e-8 if prec == "fp64" else 1e-6
+    ctx = T.Context.from_problem(p)
+    for storage in (T.TBSCI_STORE_FULL, T.TBSCI_STORE_LEAN):
+        info, X = ctx.davidson(tol_resid=1e-8 if prec == "fp64" else 1e-5, n_max=6,
+                               max_iter=400, precision=pr, storage=storage)
+        assert info["status"] == 0 and info["converged"] == 1
+        assert info["lean"] == (1 if storage == T.TBSCI_STORE_LEAN else 0)
+        assert info["sector"] == -1
+        assert abs(info["energy"] - ref["lowest"]) < tol_e
+        assert abs(info["energy_other"] - ref["sym"]) < tol_e
+        assert abs(info["energy_fp64_check"] - info["energy"]) < 1e-9
+        x = X.cpu().numpy()
+        assert np.abs(x + x.T).max() < 1e-10
+        for sec, key in ((1, "sym"), (-1, "anti")):
+            i1, X1 = ctx.davidson(tol_resid=1e-8 if prec == "fp64" else 1e-5, n_max=6,
+                                  max_iter=400, precision=pr, storage=storage, sector=sec)
+            assert i1["status"] == 0 and i1["sector"] == sec
+            assert abs(i1["energy"] - ref[key]) < tol_e
+            assert np.isnan(i1["energy_other"])
+            x1 = X1.cpu().numpy()
+            assert np.abs(x1 - sec * x1.T).max() < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("n_max", [2, 3, 8])
+def test_davidson_lean_storage(env, n_max):
+    """Lean storage (2 n_max + 3 vectors: collapse restart, the image of the
+    correction in a vector of the collapsed basis, H_KK recomputed) against
+    dense diagonalisation on a space with independent lists and on a
+    complete one, FP64 and mixed; the fresh FP64 energy check agrees with
+    the reported energy."""
+    T, O, torch = env
+    for name in ("rand_m8_3_4", "fci_m8"):
+        p = PROBS[name]
+        e_ref = O.lowest_by_flip_sector(O.Space.of(p))["lowest"]
+        ctx = T.Context.from_problem(p)
+        info, X = ctx.davidson(tol_resid=1e-8, n_max=n_max, max_iter=2000,
+                               storage=T.TBSCI_STORE_LEAN)
+        assert info["status"] == 0 and info["lean"] == 1
+        assert abs(info["energy"] - e_ref) < 1e-8
+        assert abs(info["energy_fp64_check"] - info["energy"]) < 1e-10
+        im, _ = ctx.davidson(tol_resid=1e-5, n_max=n_max, max_iter=2000,
+                             precision=T.TBSCI_MIXED, storage=T.TBSCI_STORE_LEAN,
+                             want_vector=False)
+        assert im["status"] == 0 and abs(im["energy"] - e_ref) < 1e-6
+        assert abs(im["energy_fp64_check"] - im["energy"]) < 1e-8
+        ctx.close()
+
+
+def test_davidson_option_errors(env):
+    """guess_kind must match the guess pointer; an empty antisymmetric
+    sector (one string per spin) and out-of-range options are rejected."""
+    T, O, torch = env
+    p = PROBS["fci_m8"]
+    ctx = T.Context.from_problem(p)
+    X = torch.zeros((ctx.l_alpha, ctx.l_beta), dtype=torch.float64, device="cuda")
+    X[0, 0] = 1.0
+    info = T.DavidsonInfo()
+    lib = T.load()
+    for kw, guess in ((dict(guess_kind=T.TBSCI_GUESS_USER), None),
+                      (dict(guess_kind=T.TBSCI_GUESS_DIAG), X),
+                      (dict(sector=2), None), (dict(storage=5), None)):
+        o = T.make_opts(**kw)
+        rc = lib.tbsci_davidson(ctx.handle, ctypes.byref(o),
+                                ctypes.c_void_p(guess.data_ptr()) if guess is not None else None,
+                                None, ctypes.byref(info), None)
+        assert rc == T.TBSCI_E_INVAL, kw
+    ctx.close()
+    one = W.random_selection(7, 3, 3, 1, 1, seed=18)
+    one.beta = one.alpha.copy()
+    c1 = T.Context.from_problem(one)
+    with pytest.raises(T.TbsciError) as ei:
+        c1.davidson(sector=-1)
+    assert ei.value.code == T.TBSCI_E_INVAL
+    i1, _ = c1.davidson()
+    assert i1["status"] == 0 and i1["sector"] == 1 and np.isnan(i1["energy_other"])
+    c1.close()
 
 
 @pytest.mark.parametrize("shape", [(3200, 40), (40, 3200)])

@@ -48,30 +48,9 @@ def _mix():
 
 
 def _dense_e0(O, p):
-    """Lowest eigenvalue of the oracle's dense H in the sector the solvers
-    work in.  With identical alpha and beta lists (N_alpha = N_beta) H
-    commutes with the spin flip F|I J> = (-1)^N |J I>, and the solvers start
-    from a vector with C = C^T (F = (-1)^N), so the reference is the lowest
-    eigenvalue on that sector; otherwise the global lowest eigenvalue."""
-    sp = O.Space.of(p)
-    H = sp.dense_h()
-    if not (p.n_alpha == p.n_beta and np.array_equal(p.alpha, p.beta)):
-        return float(np.linalg.eigvalsh(H)[0])
-    l = len(p.alpha)
-    lam = (-1) ** p.n_alpha
-    # orthonormal basis of {v : F v = lam v}: |I I> and (|I J> + |J I>)/sqrt2
-    # (F |I J> = lam |J I>)
-    cols = []
-    for i in range(l):
-        for j in range(i, l):
-            v = np.zeros(l * l)
-            if i == j:
-                v[i * l + i] = 1.0
-            else:
-                v[i * l + j] = v[j * l + i] = 1.0 / np.sqrt(2.0)
-            cols.append(v)
-    Q = np.array(cols).T
-    return float(np.linalg.eigvalsh(Q.T @ H @ Q)[0])
+    """Lowest eigenvalue of the oracle's dense P H P (over both spin-flip
+    sectors when the alpha and beta lists are identical)."""
+    return O.lowest_by_flip_sector(O.Space.of(p))["lowest"]
 
 
 def _ref_e0(T, O, p):

@@ -302,3 +302,98 @@ def test_spin_flip_symmetry_and_singlet_sector(oracle_mod):
         C = np.random.default_rng(1).normal(size=(l, l))
         C = C + C.T
         assert np.allclose(F @ C.ravel(), (-1) ** N * C.ravel())
+
+
+def test_sigma_rows_from_and_linked_rows(oracle_mod):
+    """The row-sampled sigma used by the full-size parity tests: on selected
+    spaces where the linked rows are a small strict subset, linked_rows equals
+    a brute-force scan of excitation degrees <= 2, sigma_rows_from on just
+    those rows equals the full sigma bit for bit, and leaving out one needed
+    row raises."""
+    O = oracle_mod
+    # uniformly random selections from large string sets, so that few rows
+    # are within two excitations of a sampled row
+    cases = [W.random_selection(14, 7, 7, 300, 40, seed=21),
+             W.random_selection(14, 6, 5, 250, 60, seed=25),
+             W.random_selection(13, 5, 6, 260, 30, seed=27)]
+    for p in cases:
+        sp = O.Space.of(p)
+        la = len(p.alpha)
+        rows = np.array([0, la // 3], dtype=np.int64)
+        need = sp.linked_rows(rows)
+        a = [int(x) for x in p.alpha]
+        brute = sorted({j for r in rows for j in range(la)
+                        if bin(a[int(r)] ^ a[j]).count("1") <= 4})
+        assert need.tolist() == brute
+        assert len(need) < la // 2  # a strict, small subset
+        C = W.random_vector(la, len(p.beta), seed=5)
+        full = sp.sigma(C, rows=rows)
+        part = sp.sigma_rows_from(rows, C[need], need)
+        assert np.array_equal(full, part)
+        # the sub-matrix really is all it reads: other rows may hold anything
+        junk = C.copy()
+        others = np.setdiff1d(np.arange(la), need)
+        junk[others] = 1e300
+        assert np.array_equal(sp.sigma(junk, rows=rows), full)
+        with pytest.raises(ValueError):
+            drop = need[need != rows[1]][:-1] if len(need) > 1 else need[:0]
+            sp.sigma_rows_from(rows, C[drop], drop)
+
+
+def test_fock_spin_squared_spectrum(oracle_mod):
+    """S^2 built from Jordan-Wigner operators has eigenvalues S(S+1) with the
+    multiplicities of two-electron spin coupling (M = 2: 16 states; the
+    N_alpha = N_beta = 1 block holds 3 singlets and 1 triplet component)."""
+    O = oracle_mod
+    S2 = O.fock_spin_squared(2)
+    w = np.round(np.linalg.eigvalsh(S2), 10)
+    vals, counts = np.unique(w, return_counts=True)
+    # Fock space of 2 spatial orbitals: 1 (vacuum) + 4 doublet states x 2 ...
+    assert set(vals.tolist()) <= {0.0, 0.75, 2.0}
+    assert np.isclose(np.trace(S2), sum(v * c for v, c in zip(vals, counts)))
+    idx = [O.fock_index(a, b, 2) for a in (1, 2) for b in (1, 2)]
+    blk = np.linalg.eigvalsh(S2[np.ix_(idx, idx)])
+    assert np.allclose(np.sort(blk), [0.0, 0.0, 0.0, 2.0], atol=1e-12)
+
+
+@pytest.mark.parametrize("M,N,seed", [(4, 2, 31), (4, 1, 32), (3, 1, 33), (5, 2, 34)])
+def test_flip_sectors_are_spin_parity_sectors(oracle_mod, M, N, seed):
+    """On a complete space with N_alpha = N_beta (closed under S^2), the
+    spectrum of H on symmetric CI matrices equals its spectrum on the states
+    of even S, and on antisymmetric ones that of odd S, with S^2 built
+    independently from Jordan-Wigner operators; the lowest of both sectors is
+    the lowest eigenvalue overall."""
+    O = oracle_mod
+    p = W.make_problem("flip_pin", M, N, None, seed)
+    sp = O.Space.of(p)
+    H = sp.dense_h()
+    l = len(p.alpha)
+    idx = [O.fock_index(a, b, M) for a in p.alpha for b in p.beta]
+    S2 = O.fock_spin_squared(M)[np.ix_(idx, idx)]
+    # S^2 blocks: eigenvalue S(S+1); H within each S block
+    s2w, s2v = np.linalg.eigh(S2)
+    S = np.round((-1 + np.sqrt(1 + 4 * np.clip(s2w, 0, None))) / 2).astype(int)
+    assert np.allclose(S * (S + 1), s2w, atol=1e-9)
+    by_parity = {0: [], 1: []}
+    for s in np.unique(S):
+        Q = s2v[:, S == s]
+        by_parity[int(s) % 2] += np.linalg.eigvalsh(Q.T @ H @ Q).tolist()
+    for tau, par in ((1, 0), (-1, 1)):
+        Q = O.flip_sector_basis(l, tau)
+        sec = np.linalg.eigvalsh(Q.T @ H @ Q) if Q.shape[1] else np.zeros(0)
+        assert np.allclose(np.sort(sec), np.sort(by_parity[par]), atol=1e-10)
+    r = O.lowest_by_flip_sector(sp, H)
+    assert np.isclose(r["lowest"], np.linalg.eigvalsh(H)[0], atol=1e-12)
+    assert r["lowest"] == min(x for x in (r["sym"], r["anti"]) if x is not None)
+
+
+def test_flip_sector_ground_state_outside_symmetric_sector(oracle_mod):
+    """A problem of the smallest configuration's recipe (M = 8, N = 4, every
+    string, integral seed 100) whose lowest state is antisymmetric: the
+    symmetric sector alone would miss it by more than 0.04 Eh."""
+    O = oracle_mod
+    p = W.make_problem("anti_gs", 8, 4, None, 100)
+    r = O.lowest_by_flip_sector(O.Space.of(p))
+    assert r["sector"] == -1
+    assert r["sym"] - r["anti"] > 0.04
+    assert np.isclose(r["lowest"], r["lowest_all"], atol=1e-12)

@@ -21,6 +21,11 @@ Contents, each following the paper (arXiv 2503.10335):
 * ``sigma`` / ``diag`` / ``dense_h`` -- sigma = P H P C over the TPB space
   (Sec. II.A, Eq. TPB_Det and the beta-fastest index map; Sec. II.C,
   Slater-Condon rule and Algorithm 1's six categories).
+* ``set_dets`` / ``sigma_dets`` / ``dense_h_dets`` -- the same over a TBSCI
+  space: per alpha string w only the beta strings of its index set I_w
+  (Sec. II.A), with the membership of both the output and every
+  contributing determinant tested (Algorithm 1; its [0,2] loop writes only
+  the first test).
 * ``davidson`` -- a plain Davidson eigensolver with collapse restart
   (Sec. II.B, Davidson matrix-vector products; Sec. III.C, restart with a
   bounded number of stored vectors).
@@ -83,6 +88,9 @@ def _load():
             lib.orc_lists.argtypes = [P, i64, ctypes.c_int, ctypes.c_int, P, i64, P, P, ctypes.c_int]
             lib.orc_count_singles.restype = i64
             lib.orc_count_singles.argtypes = [P, i64, ctypes.c_int, ctypes.c_int]
+            lib.orc_set_dets.restype = ctypes.c_int
+            lib.orc_set_dets.argtypes = [P, P, P]
+            lib.orc_sigma_dets.argtypes = [P, P, P, P, P, P, P, ctypes.c_int]
             _lib = lib
     return _lib
 
@@ -160,6 +168,46 @@ class Space:
             ptr, ent = lists(self.alpha, self.M, kind, rows=rows)
             need.update(int(j) for j in ent[:, 0])
         return np.array(sorted(need), dtype=np.int64)
+
+    # ------------------------------------------ determinant-level pruning
+
+    def set_dets(self, row_off, beta_idx):
+        """Keep only some determinants (Sec. II.A, the TBSCI space): alpha
+        row w keeps the beta strings beta_idx[row_off[w]:row_off[w+1]] (caller
+        indices).  Compact vectors list the kept determinants row by row in
+        that order."""
+        self.row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+        self.beta_idx = np.ascontiguousarray(beta_idx, dtype=np.int32)
+        if len(self.row_off) != self.la + 1:
+            raise ValueError("row_off needs l_alpha + 1 entries")
+        if _load().orc_set_dets(self._p, _ptr(self.row_off), _ptr(self.beta_idx)) != 0:
+            raise ValueError("malformed determinant layout")
+
+    @property
+    def n_dets(self):
+        return int(self.row_off[-1])
+
+    def dets_index(self):
+        """Position in the [l_alpha][l_beta] TPB layout of every kept
+        determinant, in compact order."""
+        w = np.repeat(np.arange(self.la, dtype=np.int64), np.diff(self.row_off))
+        return w * self.lb + self.beta_idx.astype(np.int64)
+
+    def sigma_dets(self, c, nthreads=0):
+        """sigma_K = sum_{L kept} H_KL c_L for every kept K (compact vectors)."""
+        c = np.ascontiguousarray(c, dtype=np.float64).ravel()
+        if c.size != self.n_dets:
+            raise ValueError("c must have one entry per kept determinant")
+        out = np.empty(self.n_dets)
+        _load().orc_sigma_dets(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(self.row_off),
+                               _ptr(self.beta_idx), _ptr(c), _ptr(out), nthreads)
+        return out
+
+    def dense_h_dets(self):
+        """Dense P H P over the kept determinants: the TPB matrix restricted
+        to their rows and columns (small spaces)."""
+        k = self.dets_index()
+        return self.dense_h()[np.ix_(k, k)]
 
     def diag(self, rows=None, nthreads=0):
         if rows is None:

@@ -86,6 +86,10 @@ typedef struct {
     int64_t la, lb;
     const double *h, *eri;
     omap amap, bmap;
+    /* determinant-level pruning (NULL: every product of a selected alpha and
+     * a selected beta string): dmap maps the key ia * lb + ib of each kept
+     * determinant to its position in the compact, segment-ordered vector */
+    omap *dmap;
 } ospace;
 
 /* A determinant in spin orbitals: w[0] = alpha bits, w[1] = beta bits. */
@@ -169,14 +173,21 @@ static int64_t lookup_det(const ospace *s, const det_t *d, int64_t *col) {
 }
 
 /* C rows supplied through a map: row_slot[ia] = row of Csub holding C[ia, :],
- * or -1 if that row was not supplied (then *missing is set). */
+ * or -1 if that row was not supplied (then *missing is set).  With dmap, C
+ * is a compact vector over the kept determinants and a determinant that is
+ * not kept contributes nothing. */
 typedef struct {
     const double *C;
     const int64_t *row_slot; /* NULL: C is the full matrix */
     int *missing;
+    const omap *dmap;        /* non-NULL: compact C over the kept determinants */
 } cview;
 
 static double cget(const cview *v, int64_t ja, int64_t jb, int64_t lb) {
+    if (v->dmap) {
+        int32_t k = omap_get(v->dmap, (uint64_t)(ja * lb + jb));
+        return k < 0 ? 0.0 : v->C[k];
+    }
     if (!v->row_slot) return v->C[ja * lb + jb];
     int64_t r = v->row_slot[ja];
     if (r < 0) {
@@ -248,7 +259,58 @@ void orc_space_free(void *p) {
     ospace *s = (ospace *)p;
     if (!s) return;
     omap_free(&s->amap); omap_free(&s->bmap);
+    if (s->dmap) { omap_free(s->dmap); free(s->dmap); }
     free(s);
+}
+
+/*
+ * Determinant-level pruning (Sec. II.A, the TBSCI space): row w keeps the
+ * beta strings beta_idx[row_off[w] .. row_off[w+1]), and the compact CI
+ * vector lists the kept determinants row by row in that order.  Returns 0,
+ * or -1 on a malformed layout (offsets not nondecreasing from 0, an index
+ * outside [0, l_beta), a repeated index within a row).
+ */
+int orc_set_dets(void *p, const int64_t *row_off, const int32_t *beta_idx) {
+    ospace *s = (ospace *)p;
+    if (row_off[0] != 0) return -1;
+    int64_t n = row_off[s->la];
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t w = 0; w < s->la; ++w) {
+        if (row_off[w + 1] < row_off[w]) { free(keys); return -1; }
+        for (int64_t k = row_off[w]; k < row_off[w + 1]; ++k) {
+            if (beta_idx[k] < 0 || beta_idx[k] >= s->lb) { free(keys); return -1; }
+            keys[k] = (uint64_t)(w * s->lb + beta_idx[k]);
+        }
+    }
+    omap *m = (omap *)calloc(1, sizeof(omap));
+    int rc = omap_init(m, keys, n);
+    free(keys);
+    if (rc) { omap_free(m); free(m); return -1; }
+    if (s->dmap) { omap_free(s->dmap); free(s->dmap); }
+    s->dmap = m;
+    return 0;
+}
+
+/*
+ * sigma over the kept determinants (Algorithm 1 with both membership
+ * tests: an output determinant (w, u) is kept, and so is every connected
+ * (x, v) that contributes).  C and out are compact vectors of
+ * row_off[l_alpha] entries; (ia, ib) of entry t come from the row layout.
+ */
+void orc_sigma_dets(void *p, const uint64_t *alpha, const uint64_t *beta, const int64_t *row_off,
+                    const int32_t *beta_idx, const double *C, double *out, int nthreads) {
+    ospace *s = (ospace *)p;
+    int missing = 0;
+    cview v = {C, NULL, &missing, s->dmap};
+    int64_t n = row_off[s->la];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t w = 0; w < s->la; ++w)
+        for (int64_t k = row_off[w]; k < row_off[w + 1]; ++k)
+            out[k] = sigma_one(s, &v, w, beta_idx[k], alpha, beta);
+    (void)n;
 }
 
 /* sigma rows: rows == NULL -> all alpha rows; out is [nrows][lb] */
@@ -270,7 +332,7 @@ static void sigma_rows(ospace *s, const uint64_t *alpha, const uint64_t *beta, c
 void orc_sigma(void *p, const uint64_t *alpha, const uint64_t *beta, const double *C,
                double *out, const int64_t *rows, int64_t nrows, int nthreads) {
     int missing = 0;
-    cview v = {C, NULL, &missing};
+    cview v = {C, NULL, &missing, NULL};
     sigma_rows((ospace *)p, alpha, beta, &v, out, rows, nrows, nthreads);
 }
 
@@ -280,7 +342,7 @@ int orc_sigma_rowmap(void *p, const uint64_t *alpha, const uint64_t *beta, const
                      const int64_t *row_slot, double *out, const int64_t *rows, int64_t nrows,
                      int nthreads) {
     int missing = 0;
-    cview v = {Csub, row_slot, &missing};
+    cview v = {Csub, row_slot, &missing, NULL};
     sigma_rows((ospace *)p, alpha, beta, &v, out, rows, nrows, nthreads);
     return missing ? -1 : 0;
 }

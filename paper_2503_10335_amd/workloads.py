@@ -152,6 +152,33 @@ def random_selection(M: int, na: int, nb: int, la: int, lb: int, seed: int,
                    np.ascontiguousarray(b), dict(seed=seed))
 
 
+def dets_random(la: int, lb: int, keep: float, seed: int):
+    """A ragged determinant layout: each (alpha row w, beta string u) kept
+    with probability `keep` (seeded), so rows differ in length and some may be
+    empty.  Returns (row_off int64[la+1], beta_idx int32, ascending in a row)."""
+    rng = np.random.default_rng(seed)
+    m = rng.random((la, lb)) < keep
+    row_off = np.zeros(la + 1, dtype=np.int64)
+    row_off[1:] = np.cumsum(m.sum(axis=1))
+    beta_idx = np.nonzero(m)[1].astype(np.int32)
+    return row_off, beta_idx
+
+
+def dets_rank_sum(la: int, lb: int, frac: float):
+    """Determinant layout that pairs important strings with important ones:
+    with strings in rank order, (w, u) is kept when w / la + u / lb <= t, t
+    chosen so that about `frac` of the TPB space is kept (a staircase of
+    contiguous intervals; the structure of a weight-screened product space)."""
+    t = float(np.sqrt(2.0 * frac)) if frac <= 0.5 else 2.0 - float(np.sqrt(2.0 * (1.0 - frac)))
+    w = np.arange(la) / la
+    n = np.clip(np.floor((t - w) * lb) + 1, 0, lb).astype(np.int64)
+    row_off = np.zeros(la + 1, dtype=np.int64)
+    row_off[1:] = np.cumsum(n)
+    beta_idx = np.concatenate([np.arange(k, dtype=np.int32) for k in n]) if la else \
+        np.zeros(0, dtype=np.int32)
+    return row_off, beta_idx
+
+
 def random_vector(n_alpha_rows: int, n_beta_cols: int, seed: int = 7) -> np.ndarray:
     """N(0,1) CI matrix [l_alpha][l_beta], normalised to unit 2-norm."""
     rng = np.random.default_rng(seed)

@@ -397,3 +397,94 @@ def test_flip_sector_ground_state_outside_symmetric_sector(oracle_mod):
     assert r["sector"] == -1
     assert r["sym"] - r["anti"] > 0.04
     assert np.isclose(r["lowest"], r["lowest_all"], atol=1e-12)
+
+
+# ------------------------------------------------ TBSCI (pruned) spaces
+
+def _pruned(O, p, keep, seed):
+    sp = O.Space.of(p)
+    ro, bi = W.dets_random(len(p.alpha), len(p.beta), keep, seed)
+    sp.set_dets(ro, bi)
+    return sp
+
+
+@pytest.mark.parametrize("na,nb,la,lb,keep,seed", [
+    (2, 2, 6, 6, 0.5, 41), (1, 2, 4, 6, 0.4, 42), (3, 1, 4, 4, 0.7, 43), (2, 3, 5, 4, 0.3, 44)])
+def test_dets_elements_match_jordan_wigner(oracle_mod, fock4, na, nb, la, lb, keep, seed):
+    """sigma over a ragged TBSCI space, applied to every unit vector, equals
+    the Jordan-Wigner Fock-space H restricted to the kept determinants."""
+    O = oracle_mod
+    M, h, eri, H = fock4
+    rng = np.random.default_rng(seed)
+    A, B = W.all_strings(M, na), W.all_strings(M, nb)
+    a = A[rng.permutation(len(A))[:la]]
+    b = B[rng.permutation(len(B))[:lb]]
+    sp = O.Space(M, na, nb, h, eri, a, b)
+    ro, bi = W.dets_random(len(a), len(b), keep, seed)
+    sp.set_dets(ro, bi)
+    n = sp.n_dets
+    assert 0 < n < len(a) * len(b) and (np.diff(ro) == 0).any() or n > 0
+    Hd = np.array([sp.sigma_dets(np.eye(n)[k]) for k in range(n)]).T
+    keys = sp.dets_index()
+    idx = [O.fock_index(a[k // len(b)], b[k % len(b)], M) for k in keys]
+    assert np.abs(Hd - H[np.ix_(idx, idx)]).max() <= 1e-12 * max(1.0, np.abs(H).max())
+
+
+def test_dets_sigma_is_restricted_tpb_sigma(oracle_mod):
+    """sigma over kept determinants equals the TPB sigma of the vector
+    extended by zeros, read at the kept determinants (the projector onto the
+    TBSCI space is diagonal in the TPB basis); keeping everything gives the
+    TPB sigma bit for bit."""
+    O = oracle_mod
+    for p, keep in ((W.make_problem("d12", 12, 6, 150, 51, 52, independent_beta=True), 0.3),
+                    (W.random_selection(10, 4, 5, 90, 70, seed=53), 0.6)):
+        sp = _pruned(O, p, keep, 54)
+        k = sp.dets_index()
+        c = np.random.default_rng(5).normal(size=sp.n_dets)
+        full = np.zeros(sp.la * sp.lb)
+        full[k] = c
+        ref = O.Space.of(p).sigma(full).ravel()[k]
+        got = sp.sigma_dets(c)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+        every = O.Space.of(p)
+        every.set_dets(np.arange(sp.la + 1, dtype=np.int64) * sp.lb,
+                       np.tile(np.arange(sp.lb, dtype=np.int32), sp.la))
+        cf = np.random.default_rng(6).normal(size=sp.la * sp.lb)
+        assert np.array_equal(every.sigma_dets(cf), O.Space.of(p).sigma(cf).ravel())
+
+
+def test_dets_hermitian_and_interlacing(oracle_mod):
+    """The TBSCI matrix is symmetric, its lowest eigenvalue lies above that
+    of the TPB space, and growing the kept set (nested layouts) never raises
+    it (Cauchy interlacing)."""
+    O = oracle_mod
+    p = W.make_problem("d10", 10, 5, 40, 61, 62)
+    tpb = O.Space.of(p)
+    e_tpb = np.linalg.eigvalsh(tpb.dense_h())[0]
+    la, lb = len(p.alpha), len(p.beta)
+    prev = None
+    for frac in (0.15, 0.3, 0.6, 1.0):
+        sp = O.Space.of(p)
+        sp.set_dets(*W.dets_rank_sum(la, lb, frac))
+        Hd = sp.dense_h_dets()
+        c = np.random.default_rng(7).normal(size=(sp.n_dets, 3))
+        Hc = np.stack([sp.sigma_dets(c[:, j]) for j in range(3)], axis=1)
+        assert np.abs(Hc - Hd @ c).max() <= 1e-12 * np.abs(Hd @ c).max()
+        assert np.abs(Hd - Hd.T).max() == 0.0
+        e = np.linalg.eigvalsh(Hd)[0]
+        assert e >= e_tpb - 1e-12
+        if prev is not None:
+            assert e <= prev + 1e-12
+        prev = e
+    assert abs(prev - e_tpb) < 1e-10
+
+
+def test_dets_layout_errors(oracle_mod):
+    O = oracle_mod
+    p = W.random_selection(8, 3, 3, 10, 12, seed=63)
+    sp = O.Space.of(p)
+    for ro, bi in (([1] + [0] * 10, [0]),                       # offsets not from 0
+                   ([0, 2] + [2] * 9, [0, 12]),                 # index out of range
+                   ([0, 2] + [2] * 9, [3, 3])):                 # repeated index
+        with pytest.raises(ValueError):
+            sp.set_dets(np.array(ro), np.array(bi))

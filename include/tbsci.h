@@ -104,6 +104,23 @@ int tbsci_dims(const tbsci_ctx *ctx, int64_t *l_alpha, int64_t *l_beta, int64_t 
 int tbsci_sigma(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precision, void *stream);
 
 /*
+ * tbsci_sigma without any allocation, for callers that cannot allocate
+ * device memory (code under HIP stream capture, serving loops or
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors as
+ * tbsci_sigma.  Its one scratch buffer -- the beta sweep's transposed block
+ * of C and the block's sweep result -- is a 64 MiB static device array
+ * owned by the library, one per device, held from the library's first use
+ * on that device until the process ends; the beta sweep runs in blocks of
+ * alpha rows that fit in it.  Every call on one device shares that array
+ * and leaves its contents behind, so calls that overlap on one device (on
+ * different streams or threads) race; serialise them.  Spaces whose
+ * l_beta exceeds 4,194,304 strings (one alpha row does not fit) fail with
+ * TBSCI_E_INVAL.  No events are recorded for tbsci_timing_*.
+ */
+int tbsci_sigma_noalloc(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precision,
+                        void *stream);
+
+/*
  * One or more of the three terms of sigma, for verification and
  * measurement: terms is a bit mask, 1 = same-spin alpha (A_a C), 2 =
  * same-spin beta (C A_b^T), 4 = opposite spin (sum (pq|rs) E^a_pq C

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtbsci.so")
-SOURCES = ["api.hip", "index_kernels.hip", "sigma_kernels.hip", "davidson.hip", "batch.hip", "server.hip"]
+SOURCES = ["api.hip", "index_kernels.hip", "sigma_kernels.hip", "davidson.hip", "batch.hip", "server.hip",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

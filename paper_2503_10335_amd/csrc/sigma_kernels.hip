@@ -992,10 +992,14 @@ __global__ __launch_bounds__(kBlock) void k_ab_direct(int64_t lb, int64_t ncb, i
 // sigma with the beta sweep in blocks of rb alpha rows; work holds
 // 2 l_beta rb elements of type T (C^T and the sweep result of a block)
 template <typename T>
-void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work, int64_t rb) {
+void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work, int64_t rb,
+                bool marks) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     const int64_t la = A.l, lb = B.l;
     const int prec = sizeof(T) == 8 ? TBSCI_FP64 : TBSCI_FP32;
+    auto timing_mark = [&](Ctx &cc, int index, int pr, hipStream_t s2) {
+        if (marks) ::tbsci::timing_mark(cc, index, pr, s2);
+    };
 
     timing_mark(c, 0, prec, st);
     if (terms & 1)
@@ -1179,7 +1183,7 @@ void timing_clear(Ctx &c) {
 }
 
 void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
-                     void *work, size_t work_bytes) {
+                     void *work, size_t work_bytes, bool marks) {
     const int64_t la = c.sp[0].l, lb = c.sp[1].l;
     int64_t rb = la;
     if (terms & 2) {
@@ -1188,14 +1192,14 @@ void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t 
             throw Error(TBSCI_E_INVAL, "the workspace cannot hold the beta sweep of one alpha row");
     }
     if (precision == TBSCI_FP64)
-        sigma_impl<double>(c, (const double *)C, (double *)S, st, terms, work, rb);
+        sigma_impl<double>(c, (const double *)C, (double *)S, st, terms, work, rb, marks);
     else
-        sigma_impl<float>(c, (const float *)C, (float *)S, st, terms, work, rb);
+        sigma_impl<float>(c, (const float *)C, (float *)S, st, terms, work, rb, marks);
 }
 
 void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms) {
     void *w = ctx_workspace(c);
-    launch_sigma_ws(c, C, S, precision, st, terms, w, c.work_bytes);
+    launch_sigma_ws(c, C, S, precision, st, terms, w, c.work_bytes, true);
 }
 
 // Floating-point operations one launch of kernel `kernel` executes: for the

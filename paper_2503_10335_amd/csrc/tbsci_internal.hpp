@@ -239,9 +239,11 @@ void launch_full_diag(const Ctx &c, double *out, hipStream_t st);
 // sigma with the context's workspace (allocated on first use)
 void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms = 7);
 // sigma with a caller-provided workspace of work_bytes bytes (the beta
-// sweep runs in blocks that fit; throws TBSCI_E_INVAL when one row does not)
+// sweep runs in blocks that fit; throws TBSCI_E_INVAL when one row does
+// not); marks: record the measurement events when timing is on (they are
+// created on first use, an allocation)
 void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
-                     void *work, size_t work_bytes);
+                     void *work, size_t work_bytes, bool marks);
 double executed_flops(Ctx &c, int kernel, int precision);
 // sigma of n problems in shared launches (one per kernel type, the
 // opposite-spin term one per group of equal tile shape); C[i], S[i] are

@@ -93,6 +93,7 @@ def load():
         "tbsci_dims": (c_int, [P, P, P, P]),
         "tbsci_sigma": (c_int, [P, P, P, c_int, P]),
         "tbsci_sigma_terms": (c_int, [P, P, P, c_int, c_int, P]),
+        "tbsci_sigma_noalloc": (c_int, [P, P, P, c_int, P]),
         "tbsci_diag": (c_int, [P, P, P]),
         "tbsci_davidson_default_opts": (None, [P]),
         "tbsci_davidson": (c_int, [P, P, P, P, P, P]),
@@ -170,6 +171,12 @@ def tbsci_dims(ctx):
 def tbsci_sigma(ctx, C, S, precision=TBSCI_FP64, stream=None):
     _check(load().tbsci_sigma(ctx, ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(S.data_ptr()),
                               int(precision), _stream(stream)))
+
+
+def tbsci_sigma_noalloc(ctx, C, S, precision=TBSCI_FP64, stream=None):
+    _check(load().tbsci_sigma_noalloc(ctx, ctypes.c_void_p(C.data_ptr()),
+                                      ctypes.c_void_p(S.data_ptr()), int(precision),
+                                      _stream(stream)))
 
 
 def tbsci_sigma_terms(ctx, C, S, precision=TBSCI_FP64, terms=7, stream=None):

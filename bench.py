@@ -230,6 +230,8 @@ def parse():
     ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--davidson-workload", default="sel_m16",
                     help="workload of the Davidson leg ('' skips it)")
+    ap.add_argument("--no-davidson", action="store_true",
+                    help="skip the Davidson leg (same as --davidson-workload '')")
     ap.add_argument("--davidson-n-max", type=int, default=8)
     ap.add_argument("--davidson-tol", type=float, default=1e-4,
                     help="FP64 residual norm that ends the timed solves")
@@ -525,6 +527,8 @@ def main():
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.summary_out, args.command, args.title)
         return
+    if args.no_davidson:
+        args.davidson_workload = ""
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only (one process holds the whole CI "

@@ -88,8 +88,36 @@ int tbsci_create(int M, int n_alpha, int n_beta, const double *h, const double *
 /* Free the context and its device memory.  NULL-safe. */
 void tbsci_destroy(tbsci_ctx *ctx);
 
-/* Sizes: l_alpha, l_beta and n_det = l_alpha * l_beta (any output may be NULL). */
+/*
+ * Sizes: l_alpha, l_beta and n_det = l_alpha * l_beta, or the number of kept
+ * determinants of a TBSCI space (tbsci_set_dets).  Any output may be NULL.
+ */
 int tbsci_dims(const tbsci_ctx *ctx, int64_t *l_alpha, int64_t *l_beta, int64_t *n_det);
+
+/*
+ * Restrict the context to a TBSCI space (Sec. II.A: determinant-level
+ * pruning of the TPB space; alpha string w is paired only with the beta
+ * strings of its index set I_w, the CI vector is stored segment by segment
+ * with per-segment offsets and lengths; Algorithm 1: an element enters sigma
+ * only when both its determinants are kept).
+ *
+ *   row_off   host, l_alpha + 1 entries: row w's segment is
+ *             [row_off[w], row_off[w+1]); row_off[0] = 0, nondecreasing,
+ *             at most l_beta per row; n_det = row_off[l_alpha] >= 1
+ *   beta_idx  host, n_det caller beta indices, ascending within a row
+ * Both NULL: back to the whole TPB space.  Afterwards tbsci_sigma,
+ * tbsci_sigma_terms, tbsci_diag and tbsci_davidson take and return compact
+ * vectors of n_det elements in that order (sigma = P H P C with P the
+ * projector onto the kept determinants).  The sigma kernels run on the
+ * vector extended by zeros to [l_alpha][l_beta] and read the kept entries
+ * back (exact, at the cost of the TPB space's work); the context holds two
+ * such FP64 vectors, allocated on the first compact sigma, and the solver
+ * keeps its vectors in that layout.  A space that maps onto itself under
+ * (w, u) -> (u, w) keeps the spin-flip sectors of identical lists.
+ * tbsci_sigma_batch and tbsci_sigma_noalloc reject TBSCI spaces.
+ * TBSCI_E_INVAL for a malformed layout (the previous space stays).
+ */
+int tbsci_set_dets(tbsci_ctx *ctx, const int64_t *row_off, const int32_t *beta_idx);
 
 /*
  * sigma = P H P C (Sec. II.B: the matrix-vector product W = H U that

@@ -90,7 +90,8 @@ def _load():
             lib.orc_count_singles.argtypes = [P, i64, ctypes.c_int, ctypes.c_int]
             lib.orc_set_dets.restype = ctypes.c_int
             lib.orc_set_dets.argtypes = [P, P, P]
-            lib.orc_sigma_dets.argtypes = [P, P, P, P, P, P, P, ctypes.c_int]
+            lib.orc_sigma_dets.argtypes = [P, P, P, P, P, P, P, P, i64, ctypes.c_int]
+            lib.orc_dense_dets.argtypes = [P, P, P, P, P, P, ctypes.c_int]
             _lib = lib
     return _lib
 
@@ -193,21 +194,33 @@ class Space:
         w = np.repeat(np.arange(self.la, dtype=np.int64), np.diff(self.row_off))
         return w * self.lb + self.beta_idx.astype(np.int64)
 
-    def sigma_dets(self, c, nthreads=0):
-        """sigma_K = sum_{L kept} H_KL c_L for every kept K (compact vectors)."""
+    def sigma_dets(self, c, rows=None, nthreads=0):
+        """sigma_K = sum_{L kept} H_KL c_L for every kept K (compact vectors);
+        with rows, only the segments of those alpha rows, concatenated."""
         c = np.ascontiguousarray(c, dtype=np.float64).ravel()
         if c.size != self.n_dets:
             raise ValueError("c must have one entry per kept determinant")
-        out = np.empty(self.n_dets)
+        if rows is None:
+            out = np.empty(self.n_dets)
+            r, nr = None, 0
+        else:
+            r = np.ascontiguousarray(rows, dtype=np.int64)
+            nr = len(r)
+            out = np.empty(int(np.sum(self.row_off[r + 1] - self.row_off[r])))
         _load().orc_sigma_dets(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(self.row_off),
-                               _ptr(self.beta_idx), _ptr(c), _ptr(out), nthreads)
+                               _ptr(self.beta_idx), _ptr(c), _ptr(out), _ptr(r), nr, nthreads)
         return out
 
-    def dense_h_dets(self):
-        """Dense P H P over the kept determinants: the TPB matrix restricted
-        to their rows and columns (small spaces)."""
-        k = self.dets_index()
-        return self.dense_h()[np.ix_(k, k)]
+    def dense_h_dets(self, nthreads=0):
+        """Dense P H P over the kept determinants, element by element with the
+        generic Slater-Condon rule (small spaces)."""
+        n = self.n_dets
+        if n > 6000:
+            raise ValueError("dense H only for small spaces")
+        H = np.empty((n, n))
+        _load().orc_dense_dets(self._p, _ptr(self.alpha), _ptr(self.beta), _ptr(self.row_off),
+                               _ptr(self.beta_idx), _ptr(H), nthreads)
+        return H
 
     def diag(self, rows=None, nthreads=0):
         if rows is None:

@@ -298,19 +298,30 @@ int orc_set_dets(void *p, const int64_t *row_off, const int32_t *beta_idx) {
  * row_off[l_alpha] entries; (ia, ib) of entry t come from the row layout.
  */
 void orc_sigma_dets(void *p, const uint64_t *alpha, const uint64_t *beta, const int64_t *row_off,
-                    const int32_t *beta_idx, const double *C, double *out, int nthreads) {
+                    const int32_t *beta_idx, const double *C, double *out, const int64_t *rows,
+                    int64_t nrows, int nthreads) {
+    /* rows == NULL: every kept determinant, out in compact order; else only
+     * the segments of the listed alpha rows, concatenated in list order */
     ospace *s = (ospace *)p;
     int missing = 0;
     cview v = {C, NULL, &missing, s->dmap};
-    int64_t n = row_off[s->la];
+    int64_t nr = rows ? nrows : s->la;
+    int64_t *dst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nr + 1));
+    dst[0] = 0;
+    for (int64_t r = 0; r < nr; ++r) {
+        int64_t w = rows ? rows[r] : r;
+        dst[r + 1] = dst[r] + row_off[w + 1] - row_off[w];
+    }
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 1)
 #endif
-    for (int64_t w = 0; w < s->la; ++w)
+    for (int64_t r = 0; r < nr; ++r) {
+        int64_t w = rows ? rows[r] : r;
         for (int64_t k = row_off[w]; k < row_off[w + 1]; ++k)
-            out[k] = sigma_one(s, &v, w, beta_idx[k], alpha, beta);
-    (void)n;
+            out[dst[r] + k - row_off[w]] = sigma_one(s, &v, w, beta_idx[k], alpha, beta);
+    }
+    free(dst);
 }
 
 /* sigma rows: rows == NULL -> all alpha rows; out is [nrows][lb] */
@@ -394,6 +405,25 @@ void orc_dense(void *p, const uint64_t *alpha, const uint64_t *beta, double *H, 
             H[K * n + L] = orc_element(p, alpha[ia], beta[ib], alpha[ja], beta[jb]);
         }
     }
+}
+
+/* Dense P H P over the kept determinants of a TBSCI layout, [n][n]. */
+void orc_dense_dets(void *p, const uint64_t *alpha, const uint64_t *beta, const int64_t *row_off,
+                    const int32_t *beta_idx, double *H, int nthreads) {
+    ospace *s = (ospace *)p;
+    int64_t n = row_off[s->la];
+    int64_t *wa = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t w = 0; w < s->la; ++w)
+        for (int64_t k = row_off[w]; k < row_off[w + 1]; ++k) wa[k] = w;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t K = 0; K < n; ++K)
+        for (int64_t L = 0; L < n; ++L)
+            H[K * n + L] = orc_element(p, alpha[wa[K]], beta[beta_idx[K]], alpha[wa[L]],
+                                       beta[beta_idx[L]]);
+    free(wa);
 }
 
 /* Diagonal H_KK for selected rows (rows NULL -> all), [nrows][lb]. */

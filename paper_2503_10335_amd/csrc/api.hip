@@ -84,6 +84,7 @@ void destroy_ctx(Ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     timing_clear(*c);
+    free_dets(*c);
     for (auto &s : c->sp) free_spin(s);
     void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work};
     for (void *p : ptrs)
@@ -116,6 +117,21 @@ void check_ctx(const tbsci_ctx *ctx) {
 }
 
 void check_dev(const void *p, int device, const char *name) { check_device_ptr(p, device, name); }
+
+// sigma on the context's space: the TPB space, or a TBSCI space with
+// compact vectors (zero-extended into the context's two dense vectors)
+void sigma_any(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms) {
+    if (!c.dets) {
+        launch_sigma(c, C, S, precision, st, terms);
+        return;
+    }
+    const size_t sz = precision == TBSCI_FP64 ? 8 : 4;
+    double *X = dets_work(c);
+    double *Y = X + c.sp[0].l * c.sp[1].l;
+    dets_expand(c, C, X, sz, st);
+    launch_sigma(c, X, Y, precision, st, terms);
+    dets_gather(c, Y, S, sz, st);
+}
 
 }  // namespace tbsci
 
@@ -217,8 +233,9 @@ Ctx *create_ctx(int M, int n_alpha, int n_beta, const double *h, const double *e
             c->sp[0].l = l_alpha;
             c->sp[1].n = n_beta;
             c->sp[1].l = l_beta;
-            c->flip = n_alpha == n_beta && l_alpha == l_beta &&
-                      std::equal(alpha, alpha + l_alpha, beta);
+            c->flip_lists = n_alpha == n_beta && l_alpha == l_beta &&
+                            std::equal(alpha, alpha + l_alpha, beta);
+            c->flip = c->flip_lists;
             const size_t M2 = (size_t)M * M, M4 = M2 * M2, P = c->P;
             std::vector<double> V64(P * P);
             std::vector<float> V32(P * P);
@@ -291,7 +308,7 @@ int tbsci_dims(const tbsci_ctx *ctx, int64_t *l_alpha, int64_t *l_beta, int64_t 
         const Ctx *c = ctx_of(ctx);
         if (l_alpha) *l_alpha = c->sp[0].l;
         if (l_beta) *l_beta = c->sp[1].l;
-        if (n_det) *n_det = c->sp[0].l * c->sp[1].l;
+        if (n_det) *n_det = c->dets ? c->dets->n : c->sp[0].l * c->sp[1].l;
         return TBSCI_OK;
     });
 }
@@ -305,7 +322,7 @@ int tbsci_sigma(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int precisio
         check_dev(C_dev, c->device, "C");
         check_dev(sigma_dev, c->device, "sigma");
         if (C_dev == sigma_dev) throw Error(TBSCI_E_INVAL, "C and sigma must not alias");
-        launch_sigma(*c, C_dev, sigma_dev, precision, (hipStream_t)stream);
+        sigma_any(*c, C_dev, sigma_dev, precision, (hipStream_t)stream, 7);
         return TBSCI_OK;
     });
 }
@@ -321,7 +338,7 @@ int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int pr
         check_dev(C_dev, c->device, "C");
         check_dev(sigma_dev, c->device, "sigma");
         if (C_dev == sigma_dev) throw Error(TBSCI_E_INVAL, "C and sigma must not alias");
-        launch_sigma(*c, C_dev, sigma_dev, precision, (hipStream_t)stream, terms);
+        sigma_any(*c, C_dev, sigma_dev, precision, (hipStream_t)stream, terms);
         return TBSCI_OK;
     });
 }
@@ -331,7 +348,13 @@ int tbsci_diag(tbsci_ctx *ctx, double *diag_dev, void *stream) {
         check_ctx(ctx);
         Ctx *c = ctx_of(ctx);
         check_dev(diag_dev, c->device, "diag");
-        launch_full_diag(*c, diag_dev, (hipStream_t)stream);
+        if (c->dets) {  // H_KK of the kept determinants, compact
+            double *X = dets_work(*c);
+            launch_full_diag(*c, X, (hipStream_t)stream);
+            dets_gather(*c, X, diag_dev, 8, (hipStream_t)stream);
+        } else {
+            launch_full_diag(*c, diag_dev, (hipStream_t)stream);
+        }
         return TBSCI_OK;
     });
 }

@@ -55,7 +55,16 @@ struct VDesc {
     int32_t M, pad;
     const uint64_t *astr;
     const double *da, *db, *jb;
+    const uint32_t *mask;  // TBSCI space: kept determinants (bit u of row w), else null
+    int64_t wpr;
 };
+
+// whether determinant t of a slot's zero-extended layout belongs to its space
+__device__ __forceinline__ bool kept(const VDesc &e, int64_t t) {
+    if (!e.mask) return true;
+    const int64_t w = t / e.lb, u = t - w * e.lb;
+    return (e.mask[w * e.wpr + (u >> 5)] >> (u & 31)) & 1u;
+}
 
 __device__ __forceinline__ const VDesc &slot_of(const VDesc *__restrict__ d, int nd, int64_t &lblk) {
     int lo = 0, hi = nd - 1;
@@ -173,6 +182,7 @@ __global__ __launch_bounds__(kB) void gv_diag_min(const VDesc *__restrict__ d, i
     int64_t bi = -1;
     TB_SLOT_LOOP(e, lb, t) {
         if (e.flip < 0 && t / e.lb == t % e.lb) continue;
+        if (!kept(e, t)) continue;
         const double v = diag_at(e, t);
         if (v < best) {
             best = v;
@@ -507,6 +517,13 @@ __global__ __launch_bounds__(kB) void gv_flip_sym(const VDesc *__restrict__ d, i
     flip_sym_block(lb, e.lb, (double)e.flip, e.o0);
 }
 
+// zero the entries of o0 outside the slot's TBSCI space
+__global__ __launch_bounds__(kB) void gv_mask(const VDesc *__restrict__ d, int nd) {
+    int64_t lb;
+    const VDesc e = slot_of(d, nd, lb);
+    TB_SLOT_LOOP(e, lb, t) if (!kept(e, t)) e.o0[t] = 0.0;
+}
+
 __global__ __launch_bounds__(kB) void gv_to_f32(const VDesc *__restrict__ d, int nd) {
     int64_t lb;
     const VDesc e = slot_of(d, nd, lb);
@@ -534,13 +551,14 @@ enum Op {
     O_CVT32,
     O_SIGMA,  // marker: grouped sigma builds
     O_CVT64,
+    O_MASK,                                         // TBSCI space: sigma restricted to it
     O_COL_D, O_COL_R,                               // new column of V^T H V
     O_N
 };
 
 enum Kind {
     K_DIAG, K_FILL, K_COPY, K_DMIN, K_AMIN, K_AMAX, K_ASIGN, K_SCOPY, K_RITZ, K_RED, K_SYM, K_LC,
-    K_DOT, K_SUB, K_SUBDOT, K_SUBNORM, K_SCALE, K_F32, K_F64, K_NONE
+    K_DOT, K_SUB, K_SUBDOT, K_SUBNORM, K_SCALE, K_F32, K_F64, K_MASK, K_NONE
 };
 
 Kind kind_of(int op) {
@@ -562,6 +580,7 @@ Kind kind_of(int op) {
         case O_GN_S: case O_N2_S: case O_TSCALE: return K_SCALE;
         case O_CVT32: return K_F32;
         case O_CVT64: return K_F64;
+        case O_MASK: return K_MASK;
         case O_SIGMA: return K_NONE;
         case O_GN_R: case O_RITZ_R: case O_RO1_R: case O_RO2_R: case O_N2_R: case O_G0_R:
         case O_G1_R: case O_D1_R: case O_S1D2_R: case O_S2N_R: case O_COL_R: return K_RED;
@@ -623,9 +642,9 @@ BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o, bool gue
     // the sector asked for, or in both (symmetric first)
     int sector = 0, npass = 1;
     if (c->flip && !guess) {
-        const bool anti_empty = c->sp[0].l < 2;
+        const bool anti_empty = c->sp[0].l < 2 || (c->dets && !c->dets->open_pairs);
         if (o.sector == -1 && anti_empty)
-            throw Error(TBSCI_E_INVAL, "the antisymmetric sector of a one-string space is empty");
+            throw Error(TBSCI_E_INVAL, "the antisymmetric sector of this space is empty");
         sector = o.sector != 0 ? o.sector : 1;
         npass = (o.sector == 0 && !anti_empty) ? 2 : 1;
     }
@@ -748,6 +767,16 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         d.da = s.c->sp[0].dsame;
         d.db = s.c->sp[1].dsame;
         d.jb = s.c->sp[1].jocc;
+        d.mask = s.c->dets ? s.c->dets->mask : nullptr;
+        d.wpr = s.c->dets ? s.c->dets->wpr : 0;
+    };
+    // a TBSCI space: the sigma of a zero-extended vector, read on the space
+    auto mask_out = [&](double *o) {
+        if (!s.c->dets) return;
+        VDesc m = base();
+        diag_fields(m);
+        m.o0 = o;
+        S.ops[O_MASK].push_back(m);
     };
     auto take = [](std::vector<double *> &pool) {
         if (pool.empty()) throw Error(TBSCI_E_STATE, "batch slot vector pool exhausted");
@@ -777,6 +806,7 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         S.c64.push_back(s.c);
         S.i64.push_back(s.X);
         S.o64.push_back(P.W0);
+        mask_out(P.W0);
         dots(O_COL_D, {s.X, P.W0}, s.X, sCol);
         return;
     }
@@ -958,6 +988,7 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
         sig_out = P.TW;
         dots(O_COL_D, with_t, P.TW, sCol);
     }
+    mask_out(sig_out);
     if (P.sig32) {
         VDesc a = base();
         a.in = sig_in;
@@ -1035,6 +1066,7 @@ bool BatchEngine::tick() {
             case K_SCALE: gv_scale<<<g, kB, 0, st_>>>(d, nd); break;
             case K_F32: gv_to_f32<<<g, kB, 0, st_>>>(d, nd); break;
             case K_F64: gv_to_f64<<<g, kB, 0, st_>>>(d, nd); break;
+            case K_MASK: gv_mask<<<g, kB, 0, st_>>>(d, nd); break;
             case K_NONE: break;
         }
         TB_HIP(hipGetLastError());
@@ -1345,8 +1377,36 @@ int tbsci_davidson(tbsci_ctx *ctx, const tbsci_davidson_opts *opts, const double
                                        "TBSCI_GUESS_USER");
         if (guess_dev) check_dev(guess_dev, c->device, "guess");
         if (C_out_dev) check_dev(C_out_dev, c->device, "C_out");
+        hipStream_t st = (hipStream_t)stream;
+        // a TBSCI space: the solver works on zero-extended vectors; the
+        // guess and the output are compact at the boundary
+        const double *g = guess_dev;
+        double *out = C_out_dev, *gd = nullptr, *od = nullptr;
+        struct Free {
+            double **p[2];
+            ~Free() {
+                for (double **q : p)
+                    if (*q) (void)hipFree(*q);
+            }
+        } fr{{&gd, &od}};
+        if (c->dets) {
+            const size_t bytes = sizeof(double) * (size_t)(c->sp[0].l * c->sp[1].l);
+            if (guess_dev) {
+                TB_HIP(hipMalloc((void **)&gd, bytes));
+                dets_expand(*c, guess_dev, gd, 8, st);
+                g = gd;
+            }
+            if (C_out_dev) {
+                TB_HIP(hipMalloc((void **)&od, bytes));
+                out = od;
+            }
+        }
         tbsci_davidson_info tmp;
-        const int rc = solve_one(*c, o, guess_dev, C_out_dev, tmp, (hipStream_t)stream);
+        const int rc = solve_one(*c, o, g, out, tmp, st);
+        if (od) {
+            dets_gather(*c, od, C_out_dev, 8, st);
+            TB_HIP(hipStreamSynchronize(st));
+        }
         *info = tmp;
         if (rc == TBSCI_E_NOTCONV) set_error(rc, "Davidson did not reach the tolerance");
         return rc;
@@ -1367,6 +1427,8 @@ int tbsci_sigma_batch(tbsci_ctx *const *ctxs, int n, const void *const *C_dev,
             cs[i] = ctx_of(ctxs[i]);
             if (cs[i]->device != cs[0]->device)
                 throw Error(TBSCI_E_INVAL, "contexts are on different devices");
+            if (cs[i]->dets)
+                throw Error(TBSCI_E_INVAL, "tbsci_sigma_batch takes whole TPB spaces only");
             check_dev(C_dev[i], cs[i]->device, "C");
             check_dev(sigma_dev[i], cs[i]->device, "sigma");
             if (C_dev[i] == sigma_dev[i]) throw Error(TBSCI_E_INVAL, "C and sigma must not alias");

@@ -53,6 +53,9 @@ int tbsci_sigma_noalloc(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int 
         check_dev(C_dev, c->device, "C");
         check_dev(sigma_dev, c->device, "sigma");
         if (C_dev == sigma_dev) throw Error(TBSCI_E_INVAL, "C and sigma must not alias");
+        if (c->dets)
+            throw Error(TBSCI_E_INVAL, "tbsci_sigma_noalloc takes whole TPB spaces only (a "
+                                       "TBSCI space needs two zero-extended vectors)");
         if (beta_block_rows(c->sp[0].l, c->sp[1].l, kScratchBytes) < 1)
             throw Error(TBSCI_E_INVAL, "l_beta exceeds what the 64 MiB static workspace of "
                                        "tbsci_sigma_noalloc holds (4.19e6 strings)");

@@ -114,8 +114,29 @@ inline int64_t sweep_chunk(int64_t l, int64_t n_a) {
     return 0;
 }
 
+// A TBSCI space (determinant-level pruning, Sec. II.A): alpha row w keeps
+// the beta strings idx[off[w] .. off[w+1]) (caller indices, ascending).
+// Vectors at the boundary are compact, the kept determinants row by row;
+// inside, sigma runs on the zero-extended [l_alpha][l_beta] layout and
+// reads the kept entries back (the projector onto the space is diagonal in
+// the TPB basis, so this is exact), and the solver keeps its vectors in that
+// layout with every entry outside the space zero.
+struct Dets {
+    int64_t n = 0;              // kept determinants
+    int64_t *off = nullptr;     // [l_alpha + 1]
+    int32_t *idx = nullptr;     // [n]
+    uint32_t *mask = nullptr;   // [l_alpha][wpr]: bit u of row w set when (w, u) is kept
+    int64_t wpr = 0;            // 32-bit words per mask row
+    bool symmetric = false;     // (w, u) kept exactly when (u, w) is kept
+    bool open_pairs = false;    // some (w, u) with w != u is kept
+    void *work = nullptr;       // two zero-extended vectors for the compact sigma
+    size_t work_bytes = 0;
+};
+
 struct Ctx {
     int M = 0, P = 0, device = 0;
+    bool flip_lists = false;    // the alpha and beta lists are identical (see flip)
+    Dets *dets = nullptr;       // TBSCI space, or nullptr for the whole TPB space
     // alpha and beta lists are the same strings in the same order with
     // N_alpha = N_beta: H commutes with the spin flip C -> C^T (up to the
     // sign (-1)^N), and the solvers work in the C^T = C and C^T = -C
@@ -227,8 +248,22 @@ size_t ctx_bytes(const Ctx &c);
 size_t ctx_bytes_bound(int M, int n_alpha, int n_beta, int64_t l_alpha, int64_t l_beta);
 
 Ctx *ctx_of(const tbsci_ctx *p);
+// sigma on the context's space (the TPB space, or its TBSCI space with
+// compact vectors); terms as tbsci_sigma_terms
+void sigma_any(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms);
 void check_ctx(const tbsci_ctx *ctx);
 void check_dev(const void *p, int device, const char *name);
+
+// ---- dets.hip (TBSCI spaces)
+void free_dets(Ctx &c);
+// compact (dets->n entries) -> zero-extended [l_alpha][l_beta] of the same
+// type (sz = 8 or 4 bytes), and back
+void dets_expand(Ctx &c, const void *compact, void *dense, size_t sz, hipStream_t st);
+void dets_gather(Ctx &c, const void *dense, void *compact, size_t sz, hipStream_t st);
+// zero the entries of a zero-extended FP64 vector that are not kept
+void dets_mask(Ctx &c, double *dense, hipStream_t st);
+// the two zero-extended FP64 vectors of the compact sigma (allocated on first use)
+double *dets_work(Ctx &c);
 
 // ---- launchers (index_kernels.hip)
 void build_spin(Ctx &c, Spin &s, const uint64_t *host_str, hipStream_t st);

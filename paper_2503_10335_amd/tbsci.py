@@ -91,6 +91,7 @@ def load():
         "tbsci_create": (c_int, [c_int, c_int, c_int, P, P, P, i64, P, i64, c_int, P]),
         "tbsci_destroy": (None, [P]),
         "tbsci_dims": (c_int, [P, P, P, P]),
+        "tbsci_set_dets": (c_int, [P, P, P]),
         "tbsci_sigma": (c_int, [P, P, P, c_int, P]),
         "tbsci_sigma_terms": (c_int, [P, P, P, c_int, c_int, P]),
         "tbsci_sigma_noalloc": (c_int, [P, P, P, c_int, P]),
@@ -166,6 +167,15 @@ def tbsci_dims(ctx):
     la, lb, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(load().tbsci_dims(ctx, ctypes.byref(la), ctypes.byref(lb), ctypes.byref(nd)))
     return la.value, lb.value, nd.value
+
+
+def tbsci_set_dets(ctx, row_off=None, beta_idx=None):
+    if row_off is None and beta_idx is None:
+        _check(load().tbsci_set_dets(ctx, None, None))
+        return
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    bi = np.ascontiguousarray(beta_idx, dtype=np.int32)
+    _check(load().tbsci_set_dets(ctx, _np_ptr(ro), _np_ptr(bi) if bi.size else None))
 
 
 def tbsci_sigma(ctx, C, S, precision=TBSCI_FP64, stream=None):
@@ -418,6 +428,16 @@ class Context:
     def _dev(self):
         return torch.device("cuda", self.device)
 
+    def set_dets(self, row_off=None, beta_idx=None):
+        """Restrict to a TBSCI space (compact vectors afterwards); no
+        arguments: back to the whole TPB space."""
+        tbsci_set_dets(self._ctx, row_off, beta_idx)
+        self.l_alpha, self.l_beta, self.n_det = tbsci_dims(self._ctx)
+        self.compact = row_off is not None
+
+    def _shape(self):
+        return (self.n_det,) if getattr(self, "compact", False) else (self.l_alpha, self.l_beta)
+
     def mfma_flops(self, precision=TBSCI_FP64):
         """Flops one launch of the opposite-spin kernel executes (padded tiles)."""
         return tbsci_timing_executed_flops(self._ctx, 2, precision)
@@ -428,7 +448,7 @@ class Context:
             raise ValueError("C must be a contiguous device tensor of n_det elements of the "
                              "precision's type")
         if out is None:
-            out = torch.empty((self.l_alpha, self.l_beta), dtype=dt, device=C.device)
+            out = torch.empty(self._shape(), dtype=dt, device=C.device)
         elif out.dtype != dt or not out.is_contiguous() or out.numel() != self.n_det:
             raise ValueError("out must be a contiguous tensor like C")
         tbsci_sigma(self._ctx, C, out, precision, stream)
@@ -438,12 +458,12 @@ class Context:
         dt = torch.float64 if precision == TBSCI_FP64 else torch.float32
         if C.dtype != dt or not C.is_cuda or not C.is_contiguous() or C.numel() != self.n_det:
             raise ValueError("C must be a contiguous device tensor of n_det elements")
-        out = torch.empty((self.l_alpha, self.l_beta), dtype=dt, device=C.device)
+        out = torch.empty(self._shape(), dtype=dt, device=C.device)
         tbsci_sigma_terms(self._ctx, C, out, precision, terms, stream)
         return out
 
     def diag(self, stream=None):
-        D = torch.empty((self.l_alpha, self.l_beta), dtype=torch.float64, device=self._dev())
+        D = torch.empty(self._shape(), dtype=torch.float64, device=self._dev())
         tbsci_diag(self._ctx, D, stream)
         return D
 
@@ -455,7 +475,7 @@ class Context:
                       TBSCI_GUESS_USER if guess is not None else TBSCI_GUESS_DIAG)
         if guess is not None and (guess.dtype != torch.float64 or guess.numel() != self.n_det):
             raise ValueError("guess must be an FP64 device tensor of n_det elements")
-        X = torch.empty((self.l_alpha, self.l_beta), dtype=torch.float64,
+        X = torch.empty(self._shape(), dtype=torch.float64,
                         device=self._dev()) if want_vector else None
         rc, info = tbsci_davidson(self._ctx, o, guess, X, stream)
         d = info.as_dict()

@@ -446,6 +446,9 @@ def test_dets_sigma_is_restricted_tpb_sigma(oracle_mod):
         ref = O.Space.of(p).sigma(full).ravel()[k]
         got = sp.sigma_dets(c)
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+        rows = np.array([sp.la - 1, 0, sp.la // 2])
+        seg = np.concatenate([got[sp.row_off[r]:sp.row_off[r + 1]] for r in rows])
+        assert np.array_equal(sp.sigma_dets(c, rows=rows), seg)
         every = O.Space.of(p)
         every.set_dets(np.arange(sp.la + 1, dtype=np.int64) * sp.lb,
                        np.tile(np.arange(sp.lb, dtype=np.int32), sp.la))
@@ -467,6 +470,8 @@ def test_dets_hermitian_and_interlacing(oracle_mod):
         sp = O.Space.of(p)
         sp.set_dets(*W.dets_rank_sum(la, lb, frac))
         Hd = sp.dense_h_dets()
+        k = sp.dets_index()
+        assert np.array_equal(Hd, tpb.dense_h()[np.ix_(k, k)])
         c = np.random.default_rng(7).normal(size=(sp.n_dets, 3))
         Hc = np.stack([sp.sigma_dets(c[:, j]) for j in range(3)], axis=1)
         assert np.abs(Hc - Hd @ c).max() <= 1e-12 * np.abs(Hd @ c).max()

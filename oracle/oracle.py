@@ -29,6 +29,11 @@ Contents, each following the paper (arXiv 2503.10335):
 * ``davidson`` -- a plain Davidson eigensolver with collapse restart
   (Sec. II.B, Davidson matrix-vector products; Sec. III.C, restart with a
   bounded number of stored vectors).
+* ``string_irreps`` / ``symmetry_layout`` / ``symmetry_dimension`` -- the
+  irrep of a string (product over occupied orbitals) and the determinants of
+  one total irrep, as a TBSCI layout and as a count (Sec. II.A: only the
+  symmetry-allowed determinants are kept, each I_w an interval of irrep-sorted
+  beta strings; Table of the benchmark systems: their FCI dimensions).
 * ``lowest_by_flip_sector`` -- with identical alpha and beta lists, the
   lowest eigenvalue of P H P among symmetric and among antisymmetric CI
   matrices, and the lower of the two (the lowest eigenpair of Sec. II.B's
@@ -397,6 +402,55 @@ def davidson(apply_h, diag, tol=1e-8, n_max=8, max_iter=500, guess=None, floor=1
 def _fix_sign(x):
     k = int(np.argmax(np.abs(x)))
     return -x if x[k] < 0 else x
+
+
+# ------------------------------------------------- point-group symmetry
+
+def string_irreps(strings, irreps):
+    """Irrep of each string: the product (XOR of the labels) of the irreps
+    of its occupied orbitals."""
+    out = []
+    for s in np.asarray(strings, dtype=np.uint64):
+        g, v, p = 0, int(s), 0
+        while v:
+            if v & 1:
+                g ^= int(irreps[p])
+            v >>= 1
+            p += 1
+        out.append(g)
+    return np.array(out, dtype=np.int32)
+
+
+def symmetry_layout(alpha, beta, irreps, target):
+    """The determinants of total irrep `target` as a TBSCI layout (Sec. II.A:
+    the symmetry-allowed determinants, I_w = the beta strings whose irrep
+    times that of alpha string w is the target): (row_off, beta_idx)."""
+    ga, gb = string_irreps(alpha, irreps), string_irreps(beta, irreps)
+    rows = [np.nonzero((gb ^ g) == target)[0] for g in ga]
+    row_off = np.zeros(len(ga) + 1, dtype=np.int64)
+    row_off[1:] = np.cumsum([len(r) for r in rows])
+    beta_idx = (np.concatenate(rows) if rows else np.zeros(0)).astype(np.int32)
+    return row_off, beta_idx
+
+
+def symmetry_dimension(orbital_counts, n_alpha, n_beta, target, order=8):
+    """Number of determinants of total irrep `target` with n_alpha and n_beta
+    electrons in orbitals whose irreps are given as {label: count}: strings
+    counted per irrep by adding one orbital at a time."""
+    def per_irrep(n):
+        c = [[0] * order for _ in range(n + 1)]
+        c[0][0] = 1
+        for g, k in orbital_counts.items():
+            for _ in range(k):
+                new = [row[:] for row in c]
+                for j in range(n):
+                    for x in range(order):
+                        if c[j][x]:
+                            new[j + 1][x ^ g] += c[j][x]
+                c = new
+        return c[n]
+    a, b = per_irrep(n_alpha), per_irrep(n_beta)
+    return sum(a[g] * b[g ^ target] for g in range(order))
 
 
 # ------------------------------------------------------ spin-flip sectors

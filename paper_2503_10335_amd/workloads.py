@@ -124,6 +124,75 @@ def make_problem(name: str, M: int, N: int, n_keep: int | None, int_seed: int,
                    dict(int_seed=int_seed, sel_seed=sel_seed, n_keep=n_keep))
 
 
+# ------------------------------------------------------ point-group symmetry
+#
+# Irreducible representations of the abelian point groups as integer labels
+# whose product is their XOR (D2h: Ag 0, B1g 1, B2g 2, B3g 3, Au 4, B1u 5,
+# B2u 6, B3u 7; C2v: A1 0, A2 1, B1 2, B2 3).
+
+D2H = {"Ag": 0, "B1g": 1, "B2g": 2, "B3g": 3, "Au": 4, "B1u": 5, "B2u": 6, "B3u": 7}
+C2V = {"A1": 0, "A2": 1, "B1": 2, "B2": 3}
+
+
+def orbital_irreps(dist: dict, seed: int) -> np.ndarray:
+    """Irrep label of each orbital: `dist` maps label -> number of orbitals;
+    the labels are interleaved over the orbital index by a seeded shuffle (as
+    energy-ordered molecular orbitals interleave their irreps)."""
+    labels = np.array([g for g, k in sorted(dist.items()) for _ in range(k)], dtype=np.int32)
+    return labels[np.random.default_rng(seed).permutation(len(labels))]
+
+
+def integrals_sym(M: int, seed: int, irreps: np.ndarray, order: int = 8):
+    """The integral recipe of ``integrals`` (same draws), made totally
+    symmetric in the point group: h_pq = 0 unless orbitals p and q share an
+    irrep, and B^L carries the irrep L mod `order`, keeping B^L_pq only where
+    irrep(p) x irrep(q) is that irrep, so (pq|rs) = sum_L B^L_pq B^L_rs
+    vanishes unless irrep(p) x irrep(q) x irrep(r) x irrep(s) is totally
+    symmetric, and stays 8-fold symmetric and positive semidefinite."""
+    irreps = np.asarray(irreps, dtype=np.int64)
+    rng = np.random.default_rng(seed)
+    h = np.zeros((M, M))
+    for p in range(M):
+        h[p, p] = -1.0 + 2.0 * p / M
+    iu = np.triu_indices(M, 1)
+    off = rng.normal(0.0, 0.05, size=len(iu[0]))
+    off[irreps[iu[0]] != irreps[iu[1]]] = 0.0
+    h[iu] = off
+    h[(iu[1], iu[0])] = off
+    iu0 = np.triu_indices(M, 0)
+    B = np.zeros((M, M, M))
+    for L in range(M):
+        v = rng.normal(0.0, 0.15, size=len(iu0[0]))
+        v[(irreps[iu0[0]] ^ irreps[iu0[1]]) != (L % order)] = 0.0
+        B[L][iu0] = v
+        B[L][(iu0[1], iu0[0])] = v
+    eri = np.einsum("lpq,lrs->pqrs", B, B, optimize=True)
+    eri = (eri + eri.transpose(1, 0, 2, 3)) * 0.5
+    eri = (eri + eri.transpose(0, 1, 3, 2)) * 0.5
+    eri = (eri + eri.transpose(2, 3, 0, 1)) * 0.5
+    return np.ascontiguousarray(h), np.ascontiguousarray(eri)
+
+
+def make_sym_problem(name: str, M: int, N: int, dist: dict, target: int, int_seed: int,
+                     irrep_seed: int, n_keep: int | None = None, sel_seed: int | None = None,
+                     order: int = 8) -> Problem:
+    """A point-group-symmetric problem: orbital irreps from `dist`,
+    symmetric integrals, every string (or the n_keep lowest-ranked ones), the
+    same list for both spins sorted by (string irrep, integer value) so that
+    the beta strings of each irrep are contiguous.  meta holds the orbital
+    irreps and the target irrep of the determinants."""
+    irreps = orbital_irreps(dist, irrep_seed)
+    h, eri = integrals_sym(M, int_seed, irreps, order)
+    s = all_strings(M, N) if n_keep is None else select_strings(M, N, n_keep, h, sel_seed)
+    g = np.zeros(len(s), dtype=np.int64)
+    for p in range(M):
+        g ^= ((s >> np.uint64(p)) & np.uint64(1)).astype(np.int64) * int(irreps[p])
+    s = np.ascontiguousarray(s[np.lexsort((s, g))])
+    return Problem(name, M, N, N, h, eri, s, s.copy(),
+                   dict(int_seed=int_seed, irreps=irreps, target=int(target), order=order,
+                        n_keep=n_keep, sel_seed=sel_seed))
+
+
 # The five workloads: FCI-limit M=8; selected M=16 (3,000 x 3,000);
 # selected M=20 (20,000 x 20,000); FCI M=18 (48,620 x 48,620); serving mix.
 CONFIGS = {
@@ -134,7 +203,20 @@ CONFIGS = {
 }
 
 
+# A point-group-symmetric complete space: M = 14 orbitals with a D2h irrep
+# distribution shaped like a diatomic's (Ag and B1u largest), N = 7 per spin,
+# determinants of total irrep Ag (about 1/8 of the 3432 x 3432 TPB space).
+SYM_CONFIGS = {
+    "sym_m14": dict(M=14, N=7, dist={0: 3, 5: 3, 2: 2, 7: 2, 3: 1, 6: 1, 1: 1, 4: 1},
+                    target=0, int_seed=1005, irrep_seed=3005),
+}
+
+
 def config(name: str) -> Problem:
+    if name in SYM_CONFIGS:
+        c = dict(SYM_CONFIGS[name])
+        return make_sym_problem(name, c.pop("M"), c.pop("N"), c.pop("dist"), c.pop("target"),
+                                **c)
     c = dict(CONFIGS[name])
     return make_problem(name, c.pop("M"), c.pop("N"), c.pop("n_keep"), **c)
 

@@ -493,3 +493,70 @@ def test_dets_layout_errors(oracle_mod):
                    ([0, 2] + [2] * 9, [3, 3])):                 # repeated index
         with pytest.raises(ValueError):
             sp.set_dets(np.array(ro), np.array(bi))
+
+
+# ------------------------------------------------ point-group symmetry
+
+def test_symmetry_dimensions_of_the_paper_systems(oracle_mod):
+    """The determinant counts of one total irrep reproduce the FCI dimensions
+    printed for the four benchmark systems (three significant digits), and
+    the count without symmetry does not."""
+    tab = json.load(open(os.path.join(GOLDEN, "fci_dimensions.json")))
+    for r in tab["systems"]:
+        orb = {int(k): v for k, v in r["orbitals"].items()}
+        assert sum(orb.values()) == r["active"]
+        order = 8 if r["group"] == "D2h" else 4
+        d = oracle_mod.symmetry_dimension(orb, r["n_alpha"], r["n_beta"], r["target"], order)
+        assert float(f"{d:.2e}") == r["printed"], (r["name"], d)
+        full = math.comb(r["active"], r["n_alpha"]) * math.comb(r["active"], r["n_beta"])
+        assert float(f"{full:.2e}") != r["printed"]
+
+
+def test_symmetric_hamiltonian_is_block_diagonal(oracle_mod):
+    """With the symmetric integral recipe, H has no element between
+    determinants of different total irreps, the TPB spectrum is the union of
+    the spectra of the one-irrep spaces, each irrep's layout is an interval of
+    the irrep-sorted beta strings, and the counts add up."""
+    O = oracle_mod
+    dist = {0: 2, 5: 1, 2: 1, 7: 1, 6: 1}
+    p = W.make_sym_problem("sym6", 6, 3, dist, 0, 91, 92)
+    irr = p.meta["irreps"]
+    sp = O.Space.of(p)
+    H = sp.dense_h()
+    ga = O.string_irreps(p.alpha, irr)
+    gb = O.string_irreps(p.beta, irr)
+    gK = (ga[:, None] ^ gb[None, :]).ravel()
+    assert (H[gK[:, None] != gK[None, :]] == 0.0).all()
+    assert np.abs(H[gK[:, None] == gK[None, :]]).max() > 0.1
+    spec = []
+    total = 0
+    for tgt in range(8):
+        ro, bi = O.symmetry_layout(p.alpha, p.beta, irr, tgt)
+        total += int(ro[-1])
+        assert int(ro[-1]) == O.symmetry_dimension(dist, 3, 3, tgt)
+        for w in range(len(p.alpha)):
+            seg = bi[ro[w]:ro[w + 1]]
+            assert len(seg) == 0 or (np.diff(seg) == 1).all()
+        if ro[-1] == 0:
+            continue
+        s2 = O.Space.of(p)
+        s2.set_dets(ro, bi)
+        spec += np.linalg.eigvalsh(s2.dense_h_dets()).tolist()
+    assert total == len(p.alpha) * len(p.beta)
+    assert np.allclose(np.sort(spec), np.linalg.eigvalsh(H), atol=1e-11)
+
+
+def test_string_irreps_brute_force(oracle_mod):
+    """A string's irrep is the product of its occupied orbitals' irreps
+    (checked against a direct product over occupied orbitals on random
+    strings)."""
+    rng = np.random.default_rng(3)
+    irr = rng.integers(0, 8, size=20)
+    s = W.all_strings(20, 4)[rng.permutation(4845)[:200]]
+    got = oracle_mod.string_irreps(s, irr)
+    for x, g in zip(s, got):
+        occ = [p for p in range(20) if (int(x) >> p) & 1]
+        prod = 0
+        for p in occ:
+            prod = prod ^ int(irr[p])
+        assert g == prod

@@ -228,6 +228,10 @@ def parse():
                     help="comma-separated workloads whose FP64/FP32 sigma rates are reported "
                          "beside the headline ('' for none)")
     ap.add_argument("--extra-steps", type=int, default=10)
+    ap.add_argument("--tbsci-workloads", default="sym_m14,sel_m16:stair0.33",
+                    help="TBSCI spaces whose compact sigma rates are reported: a symmetric "
+                         "workload (determinants of its target irrep) or WORKLOAD:stairF "
+                         "(staircase layout keeping about F of the TPB space); '' for none")
     ap.add_argument("--davidson-workload", default="sel_m16",
                     help="workload of the Davidson leg ('' skips it)")
     ap.add_argument("--no-davidson", action="store_true",
@@ -357,6 +361,44 @@ def sigma_leg(T, torch, W, name, steps, warmup, fp32=True, keep=False):
         ctx.close()
         del C64, S64
         torch.cuda.empty_cache()
+    return out
+
+
+def tbsci_leg(T, torch, W, spec, steps, warmup):
+    """Compact sigma builds on a TBSCI space (determinant-level pruning):
+    the determinants of a symmetric workload's target irrep, or a staircase
+    layout of a workload's ranked strings.  dets/s counts kept
+    determinants."""
+    name, _, lay = spec.partition(":")
+    prob = W.config(name)
+    ctx = T.Context.from_problem(prob, device=0)
+    n_tpb = ctx.n_det
+    if lay.startswith("stair"):
+        ctx.set_dets(*W.dets_rank_sum(ctx.l_alpha, ctx.l_beta, float(lay[5:])))
+        how = f"staircase layout keeping {float(lay[5:]):g} of the TPB space"
+    else:
+        ctx.set_symmetry(prob.meta["irreps"], prob.meta["target"])
+        how = f"determinants of total irrep {prob.meta['target']} (point-group symmetry)"
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(7)
+    C = torch.randn(ctx.n_det, generator=g, device="cuda:0", dtype=torch.float64)
+    C /= torch.linalg.vector_norm(C)
+    out = dict(space=how, n_det=ctx.n_det, tpb_n_det=n_tpb)
+    for prec, key, Cp in ((T.TBSCI_FP64, "fp64", C), (T.TBSCI_FP32, "fp32", C.float())):
+        S = torch.empty_like(Cp)
+        for _ in range(warmup):
+            ctx.sigma(Cp, out=S, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.sigma(Cp, out=S, precision=prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"{key}_ms_per_step"] = 1e3 * el / steps
+        out[f"{key}_dets_per_s"] = ctx.n_det * steps / el
+    log(f"tbsci {spec}: {ctx.n_det} of {n_tpb} determinants, fp64 "
+        f"{out['fp64_ms_per_step']:.3f} ms, fp32 {out['fp32_ms_per_step']:.3f} ms")
+    ctx.close()
     return out
 
 
@@ -616,6 +658,11 @@ def main():
                            kernels_fp32=kernel_table(e["k32"]) if "k32" in e else None)
     if extra:
         result["other_workloads"] = extra
+    tb = {}
+    for spec in [w for w in args.tbsci_workloads.split(",") if w]:
+        tb[spec] = tbsci_leg(T, torch, W, spec, args.extra_steps, min(args.warmup, 3))
+    if tb:
+        result["tbsci_spaces"] = tb
 
     if args.davidson_workload:
         dv, dprob, dctx, eig = davidson_leg(T, torch, W, args)

@@ -120,6 +120,41 @@ int tbsci_dims(const tbsci_ctx *ctx, int64_t *l_alpha, int64_t *l_beta, int64_t 
 int tbsci_set_dets(tbsci_ctx *ctx, const int64_t *row_off, const int32_t *beta_idx);
 
 /*
+ * Copy the context's TBSCI layout (as given to tbsci_set_dets or built by
+ * tbsci_set_symmetry) to host buffers of l_alpha + 1 and n_det entries.
+ * TBSCI_E_STATE when the context holds the whole TPB space.
+ */
+int tbsci_get_dets(const tbsci_ctx *ctx, int64_t *row_off_host, int32_t *beta_idx_host);
+
+/*
+ * Point-group symmetry (Sec. II.A: only the symmetry-allowed determinants
+ * of the TPB space are kept; with the beta strings sorted by irrep, each
+ * I_w is one contiguous interval; Sec. II.D: alpha strings of different
+ * irreps two orbitals apart have no same-spin element).  Irreps of an
+ * abelian point group (D2h or a subgroup) are labels 0..7 whose product is
+ * their XOR; a string's irrep is the product over its occupied orbitals.
+ *
+ *   orb_irrep     host, M labels
+ *   target_irrep  the total irrep (alpha string's times beta string's) of
+ *                 the determinants kept
+ * The integrals must be totally symmetric in these irreps (h_pq = 0 across
+ * irreps, (pq|rs) = 0 unless the product of the four irreps is the totally
+ * symmetric one, both to 1e-12 of their largest element), else
+ * TBSCI_E_INVAL.  The call installs the layout of the kept determinants as
+ * tbsci_set_dets does (beta strings in the caller's order: each I_w is an
+ * interval when the caller sorted them by irrep, any subset otherwise), and
+ * drops the same-spin elements that are exactly zero (between strings of
+ * different irreps) from the sweeps' operators, which stay exact for the
+ * whole TPB space too.  Synchronous.
+ */
+int tbsci_set_symmetry(tbsci_ctx *ctx, const int32_t *orb_irrep, int32_t target_irrep);
+
+/* Irrep of every string of one spin (spin 0 = alpha), computed on the
+ * device, to a host buffer of l entries.  TBSCI_E_STATE before
+ * tbsci_set_symmetry. */
+int tbsci_string_irreps(const tbsci_ctx *ctx, int spin, int32_t *out_host);
+
+/*
  * sigma = P H P C (Sec. II.B: the matrix-vector product W = H U that
  * dominates the Davidson solver; Sec. II.C and Algorithm 1: the six
  * excitation categories [2,0] [1,1] [1,0] [0,2] [0,1] [0,0]).

@@ -126,12 +126,38 @@ int tbsci_set_dets(tbsci_ctx *ctx, const int64_t *row_off, const int32_t *beta_i
     return guarded([&]() -> int {
         check_ctx(ctx);
         Ctx *c = ctx_of(ctx);
-        const int64_t la = c->sp[0].l, lb = c->sp[1].l;
         if (!row_off && !beta_idx) {  // back to the whole TPB space
             free_dets(*c);
             c->flip = c->flip_lists;
             return TBSCI_OK;
         }
+        install_dets(*c, row_off, beta_idx);
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_get_dets(const tbsci_ctx *ctx, int64_t *row_off_host, int32_t *beta_idx_host) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        const Ctx *c = ctx_of(ctx);
+        if (!c->dets) throw Error(TBSCI_E_STATE, "the context has no TBSCI space");
+        if (!row_off_host || !beta_idx_host) throw Error(TBSCI_E_INVAL, "output is NULL");
+        TB_HIP(hipMemcpy(row_off_host, c->dets->off, sizeof(int64_t) * (c->sp[0].l + 1),
+                         hipMemcpyDeviceToHost));
+        TB_HIP(hipMemcpy(beta_idx_host, c->dets->idx, sizeof(int32_t) * c->dets->n,
+                         hipMemcpyDeviceToHost));
+        return TBSCI_OK;
+    });
+}
+
+}  // extern "C"
+
+namespace tbsci {
+
+void install_dets(Ctx &cc, const int64_t *row_off, const int32_t *beta_idx) {
+    {
+        Ctx *c = &cc;
+        const int64_t la = c->sp[0].l, lb = c->sp[1].l;
         if (!row_off || !beta_idx) throw Error(TBSCI_E_INVAL, "row_off or beta_idx is NULL");
         if (row_off[0] != 0) throw Error(TBSCI_E_INVAL, "row_off[0] must be 0");
         for (int64_t w = 0; w < la; ++w) {
@@ -184,8 +210,7 @@ int tbsci_set_dets(tbsci_ctx *ctx, const int64_t *row_off, const int32_t *beta_i
         c->dets = d;
         // the spin flip maps the space onto itself only when it is symmetric
         c->flip = c->flip_lists && sym;
-        return TBSCI_OK;
-    });
+    }
 }
 
-}  // extern "C"
+}  // namespace tbsci

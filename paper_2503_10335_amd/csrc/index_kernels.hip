@@ -468,6 +468,83 @@ void build_spin(Ctx &c, Spin &s, const uint64_t *host_str, hipStream_t st) {
     TB_HIP(hipFree(cnt));
 }
 
+namespace {
+
+// entries of each same-spin row that are kept: the diagonal (first) and
+// every element that is not exactly zero
+__global__ void k_nz_count(const int64_t *__restrict__ a_ptr, const double *__restrict__ a_val,
+                           int64_t l, int64_t *__restrict__ cnt) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= l) return;
+    int64_t n = 0;
+    for (int64_t i = a_ptr[row]; i < a_ptr[row + 1]; ++i)
+        n += (i == a_ptr[row] || a_val[i] != 0.0) ? 1 : 0;
+    cnt[row] = n;
+}
+
+__global__ void k_nz_copy(const int64_t *__restrict__ a_ptr, const int32_t *__restrict__ a_col,
+                          const double *__restrict__ a_val, const float *__restrict__ a_val32,
+                          int64_t l, const int64_t *__restrict__ n_ptr, int32_t *__restrict__ n_col,
+                          double *__restrict__ n_val, float *__restrict__ n_val32) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= l) return;
+    int64_t o = n_ptr[row];
+    for (int64_t i = a_ptr[row]; i < a_ptr[row + 1]; ++i)
+        if (i == a_ptr[row] || a_val[i] != 0.0) {
+            n_col[o] = a_col[i];
+            n_val[o] = a_val[i];
+            n_val32[o] = a_val32[i];
+            ++o;
+        }
+}
+
+}  // namespace
+
+void compact_same_spin(Ctx &c, Spin &s, hipStream_t st) {
+    (void)c;
+    const int64_t l = s.l;
+    int64_t *cnt = dalloc<int64_t>(l);
+    int64_t *np = dalloc<int64_t>(l + 1);
+    k_nz_count<<<blocks_for(l, 128), 128, 0, st>>>(s.a_ptr, s.a_val, l, cnt);
+    k_scan<<<1, 1024, 0, st>>>(cnt, l, np);
+    TB_HIP(hipGetLastError());
+    int64_t n = 0;
+    TB_HIP(hipMemcpyAsync(&n, np + l, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TB_HIP(hipStreamSynchronize(st));
+    int32_t *ncol = dalloc<int32_t>(n);
+    double *nval = dalloc<double>(n);
+    float *nval32 = dalloc<float>(n);
+    k_nz_copy<<<blocks_for(l, 128), 128, 0, st>>>(s.a_ptr, s.a_col, s.a_val, s.a_val32, l, np,
+                                                   ncol, nval, nval32);
+    TB_HIP(hipGetLastError());
+    TB_HIP(hipStreamSynchronize(st));
+    void *old[] = {s.a_ptr, s.a_col, s.a_val, s.a_val32, s.b_off, s.b_col, s.b_val, s.b_val32, cnt};
+    for (void *p : old)
+        if (p) TB_HIP(hipFree(p));
+    s.a_ptr = np;
+    s.a_col = ncol;
+    s.a_val = nval;
+    s.a_val32 = nval32;
+    s.b_off = nullptr;
+    s.b_col = nullptr;
+    s.b_val = nullptr;
+    s.b_val32 = nullptr;
+    s.n_a = n;
+    s.chunk = sweep_chunk(l, s.n_a);
+    s.nch = s.chunk ? (int)((l + s.chunk - 1) / s.chunk) : 1;
+    if (s.nch > 1) {
+        s.b_off = dalloc<int32_t>((size_t)l * (s.nch + 1));
+        s.b_col = dalloc<int32_t>(s.n_a);
+        s.b_val = dalloc<double>(s.n_a);
+        s.b_val32 = dalloc<float>(s.n_a);
+        k_chunk_rows<<<blocks_for(l, 128), 128, 0, st>>>(s.a_ptr, s.a_col, s.a_val, s.a_val32, l,
+                                                          s.nch, s.chunk, s.b_off, s.b_col,
+                                                          s.b_val, s.b_val32);
+        TB_HIP(hipGetLastError());
+        TB_HIP(hipStreamSynchronize(st));
+    }
+}
+
 void launch_lookup(const Spin &s, const uint64_t *q, int64_t n, int32_t *out, hipStream_t st) {
     if (n <= 0) return;
     k_lookup<<<blocks_for(n, kBlock), kBlock, 0, st>>>(s.keys, s.pos, s.l, q, n, out);

@@ -137,6 +137,8 @@ struct Ctx {
     int M = 0, P = 0, device = 0;
     bool flip_lists = false;    // the alpha and beta lists are identical (see flip)
     Dets *dets = nullptr;       // TBSCI space, or nullptr for the whole TPB space
+    std::vector<int32_t> irreps; // orbital irreps once a symmetry is set (else empty)
+    int target_irrep = -1;
     // alpha and beta lists are the same strings in the same order with
     // N_alpha = N_beta: H commutes with the spin flip C -> C^T (up to the
     // sign (-1)^N), and the solvers work in the C^T = C and C^T = -C
@@ -264,10 +266,15 @@ void dets_gather(Ctx &c, const void *dense, void *compact, size_t sz, hipStream_
 void dets_mask(Ctx &c, double *dense, hipStream_t st);
 // the two zero-extended FP64 vectors of the compact sigma (allocated on first use)
 double *dets_work(Ctx &c);
+// validate a layout and make it the context's space (throws TBSCI_E_INVAL)
+void install_dets(Ctx &c, const int64_t *row_off, const int32_t *beta_idx);
 
 // ---- launchers (index_kernels.hip)
 void build_spin(Ctx &c, Spin &s, const uint64_t *host_str, hipStream_t st);
 void launch_lookup(const Spin &s, const uint64_t *q, int64_t n, int32_t *out, hipStream_t st);
+// drop the same-spin elements that are exactly zero (the diagonal stays
+// first in each row) and rebuild the source-chunked copy; synchronous
+void compact_same_spin(Ctx &c, Spin &s, hipStream_t st);
 void launch_full_diag(const Ctx &c, double *out, hipStream_t st);
 
 // ---- launchers (sigma_kernels.hip)

@@ -92,6 +92,9 @@ def load():
         "tbsci_destroy": (None, [P]),
         "tbsci_dims": (c_int, [P, P, P, P]),
         "tbsci_set_dets": (c_int, [P, P, P]),
+        "tbsci_get_dets": (c_int, [P, P, P]),
+        "tbsci_set_symmetry": (c_int, [P, P, c_int]),
+        "tbsci_string_irreps": (c_int, [P, c_int, P]),
         "tbsci_sigma": (c_int, [P, P, P, c_int, P]),
         "tbsci_sigma_terms": (c_int, [P, P, P, c_int, c_int, P]),
         "tbsci_sigma_noalloc": (c_int, [P, P, P, c_int, P]),
@@ -176,6 +179,24 @@ def tbsci_set_dets(ctx, row_off=None, beta_idx=None):
     ro = np.ascontiguousarray(row_off, dtype=np.int64)
     bi = np.ascontiguousarray(beta_idx, dtype=np.int32)
     _check(load().tbsci_set_dets(ctx, _np_ptr(ro), _np_ptr(bi) if bi.size else None))
+
+
+def tbsci_get_dets(ctx, l_alpha, n_det):
+    ro = np.zeros(l_alpha + 1, dtype=np.int64)
+    bi = np.zeros(max(n_det, 1), dtype=np.int32)
+    _check(load().tbsci_get_dets(ctx, _np_ptr(ro), _np_ptr(bi)))
+    return ro, bi[:n_det]
+
+
+def tbsci_set_symmetry(ctx, orb_irrep, target_irrep):
+    g = np.ascontiguousarray(orb_irrep, dtype=np.int32)
+    _check(load().tbsci_set_symmetry(ctx, _np_ptr(g), int(target_irrep)))
+
+
+def tbsci_string_irreps(ctx, spin, l):
+    out = np.zeros(max(l, 1), dtype=np.int32)
+    _check(load().tbsci_string_irreps(ctx, int(spin), _np_ptr(out)))
+    return out[:l]
 
 
 def tbsci_sigma(ctx, C, S, precision=TBSCI_FP64, stream=None):
@@ -434,6 +455,18 @@ class Context:
         tbsci_set_dets(self._ctx, row_off, beta_idx)
         self.l_alpha, self.l_beta, self.n_det = tbsci_dims(self._ctx)
         self.compact = row_off is not None
+
+    def set_symmetry(self, orb_irrep, target_irrep):
+        """Keep the determinants of one total irrep (compact vectors afterwards)."""
+        tbsci_set_symmetry(self._ctx, orb_irrep, target_irrep)
+        self.l_alpha, self.l_beta, self.n_det = tbsci_dims(self._ctx)
+        self.compact = True
+
+    def get_dets(self):
+        return tbsci_get_dets(self._ctx, self.l_alpha, self.n_det)
+
+    def string_irreps(self, spin):
+        return tbsci_string_irreps(self._ctx, spin, self.l_alpha if spin == 0 else self.l_beta)
 
     def _shape(self):
         return (self.n_det,) if getattr(self, "compact", False) else (self.l_alpha, self.l_beta)

@@ -34,6 +34,11 @@ Contents, each following the paper (arXiv 2503.10335):
   one total irrep, as a TBSCI layout and as a count (Sec. II.A: only the
   symmetry-allowed determinants are kept, each I_w an interval of irrep-sorted
   beta strings; Table of the benchmark systems: their FCI dimensions).
+* ``string_weights`` / ``select_by_weight`` / ``coef_histogram`` -- the
+  weight of each string in a CI vector, the strings above a relative
+  threshold of the Hartree-Fock string's weight, and the histogram of the
+  coefficient magnitudes (Sec. III.B, the bitstring screening of SCI
+  wavefunctions).
 * ``lowest_by_flip_sector`` -- with identical alpha and beta lists, the
   lowest eigenvalue of P H P among symmetric and among antisymmetric CI
   matrices, and the lower of the two (the lowest eigenpair of Sec. II.B's
@@ -451,6 +456,45 @@ def symmetry_dimension(orbital_counts, n_alpha, n_beta, target, order=8):
         return c[n]
     a, b = per_irrep(n_alpha), per_irrep(n_beta)
     return sum(a[g] * b[g ^ target] for g in range(order))
+
+
+# ------------------------------------------------ string-weight selection
+
+def string_weights(C):
+    """Weights of the alpha and beta strings of a CI matrix C [l_alpha][l_beta]:
+    the sum of the squared coefficients of the determinants containing each
+    string (Sec. III.B)."""
+    C = np.asarray(C, dtype=np.float64)
+    wa = np.array([sum(float(x) * float(x) for x in row) for row in C])
+    wb = np.array([sum(float(x) * float(x) for x in col) for col in C.T])
+    return wa, wb
+
+
+def select_by_weight(strings, w, delta, ref_string):
+    """The strings whose weight exceeds delta times the weight of the
+    reference (Hartree-Fock) string, ranked heaviest first (ties: smaller
+    string first); the reference string is always kept (Sec. III.B)."""
+    strings = [int(x) for x in np.asarray(strings, dtype=np.uint64)]
+    ref = strings.index(int(ref_string))
+    thresh = delta * float(w[ref])
+    keep = [i for i in range(len(strings)) if float(w[i]) > thresh or i == ref]
+    keep.sort(key=lambda i: (-float(w[i]), strings[i]))
+    return np.array([strings[i] for i in keep], dtype=np.uint64)
+
+
+def coef_histogram(c, log10_lo, log10_hi, nbins):
+    """Counts of the coefficients by log10 |c| in nbins equal bins over
+    [log10_lo, log10_hi); smaller magnitudes (and zeros) in the first bin,
+    larger in the last."""
+    counts = [0] * nbins
+    for x in np.asarray(c, dtype=np.float64).ravel():
+        a = abs(float(x))
+        b = 0
+        if a > 0.0:
+            t = (np.log10(a) - log10_lo) * nbins / (log10_hi - log10_lo)
+            b = 0 if t < 0 else (nbins - 1 if t >= nbins else int(t))
+        counts[b] += 1
+    return np.array(counts, dtype=np.int64)
 
 
 # ------------------------------------------------------ spin-flip sectors

@@ -560,3 +560,62 @@ def test_string_irreps_brute_force(oracle_mod):
         for p in occ:
             prod = prod ^ int(irr[p])
         assert g == prod
+
+
+# ------------------------------------------------ string-weight selection
+
+def test_string_weights_closed_forms(oracle_mod):
+    """Weights of a product vector a (x) b are a^2 |b|^2 and b^2 |a|^2; the
+    alpha and beta weights of any normalised vector both sum to 1."""
+    O = oracle_mod
+    rng = np.random.default_rng(21)
+    a, b = rng.normal(size=7), rng.normal(size=5)
+    wa, wb = O.string_weights(np.outer(a, b))
+    assert np.allclose(wa, a * a * (b @ b), rtol=1e-14)
+    assert np.allclose(wb, b * b * (a @ a), rtol=1e-14)
+    C = rng.normal(size=(9, 6))
+    C /= np.linalg.norm(C)
+    wa, wb = O.string_weights(C)
+    assert abs(wa.sum() - 1) < 1e-14 and abs(wb.sum() - 1) < 1e-14
+
+
+def test_selection_is_nested_and_variational(oracle_mod):
+    """Selections by decreasing delta are nested, always hold the reference
+    string, keep every string of nonzero weight at delta = 0, and their TPB
+    ground-state energies decrease towards the complete-space energy
+    (interlacing)."""
+    O = oracle_mod
+    p = W.make_problem("sel8", 8, 4, None, 22)
+    sp = O.Space.of(p)
+    H = sp.dense_h()
+    e_all, x = O.lowest_eigpair_dense(H)
+    wa, wb = O.string_weights(x.reshape(len(p.alpha), len(p.beta)))
+    hf = int(sum(1 << q for q in range(4)))
+    prev_set, prev_e = None, None
+    for delta in (0.5, 1e-1, 1e-2, 1e-3, 1e-4, 0.0):
+        a = O.select_by_weight(p.alpha, wa, delta, hf)
+        b = O.select_by_weight(p.beta, wb, delta, hf)
+        assert int(a[0]) == hf or wa[list(map(int, p.alpha)).index(int(a[0]))] >= wa[
+            list(map(int, p.alpha)).index(hf)]
+        assert hf in set(map(int, a)) and hf in set(map(int, b))
+        s = (set(map(int, a)), set(map(int, b)))
+        if prev_set is not None:
+            assert prev_set[0] <= s[0] and prev_set[1] <= s[1]
+        sub = O.Space(8, 4, 4, p.h, p.eri, a, b)
+        e = float(np.linalg.eigvalsh(sub.dense_h())[0])
+        assert e >= e_all - 1e-12
+        if prev_e is not None:
+            assert e <= prev_e + 1e-12
+        prev_set, prev_e = s, e
+    assert len(prev_set[0]) == int((wa > 0).sum())
+    assert abs(prev_e - e_all) < 1e-10
+
+
+def test_coef_histogram_counts(oracle_mod):
+    """Histogram of log10 |c|: every coefficient counted once; values placed
+    in the bin their exponent falls in; zeros and tiny values in bin 0."""
+    O = oracle_mod
+    c = np.array([0.0, 1e-20, 3e-5, 5e-3, 0.2, 0.9, -0.05, 2.0])
+    h = O.coef_histogram(c, -6.0, 0.0, 6)
+    assert h.sum() == len(c)
+    assert h.tolist() == [2, 1, 0, 1, 1, 3]

@@ -232,6 +232,9 @@ def parse():
                     help="TBSCI spaces whose compact sigma rates are reported: a symmetric "
                          "workload (determinants of its target irrep) or WORKLOAD:stairF "
                          "(staircase layout keeping about F of the TPB space); '' for none")
+    ap.add_argument("--selection-workload", default="sym_m14",
+                    help="workload of the string-weight selection leg ('' skips it)")
+    ap.add_argument("--selection-deltas", default="1e-2,1e-3,1e-4,1e-5,1e-6,0")
     ap.add_argument("--davidson-workload", default="sel_m16",
                     help="workload of the Davidson leg ('' skips it)")
     ap.add_argument("--no-davidson", action="store_true",
@@ -400,6 +403,46 @@ def tbsci_leg(T, torch, W, spec, steps, warmup):
         f"{out['fp64_ms_per_step']:.3f} ms, fp32 {out['fp32_ms_per_step']:.3f} ms")
     ctx.close()
     return out
+
+
+def selection_leg(T, W, args):
+    """String-weight selection (the bitstring screening of SCI
+    wavefunctions): solve the workload's space (for a symmetric workload, the
+    determinants of its target irrep) to |r| <= 1e-6, weigh its strings, and
+    for each relative threshold solve the space of the strings kept; energies
+    against the reference, and the histogram of its coefficients."""
+    import numpy as np
+    import torch
+    prob = W.config(args.selection_workload)
+    sym = (prob.meta["irreps"], prob.meta["target"]) if "irreps" in prob.meta else None
+    deltas = [float(x) for x in args.selection_deltas.split(",")]
+    t0 = time.perf_counter()
+    ref, X, rows = T.selection_loop(prob, deltas, symmetry=sym, tol_resid=1e-6, n_max=8,
+                                    max_iter=2000)
+    ctx = T.Context.from_problem(prob)
+    if sym:
+        ctx.set_symmetry(*sym)
+    hist = ctx.coef_histogram(X, -14.0, 0.0, 14)
+    n_full = ctx.n_det
+    ctx.close()
+    del X
+    torch.cuda.empty_cache()
+    table = [dict(delta=r["delta"], n_strings=r["n_alpha_strings"], n_det=r["n_det"],
+                  frac_of_reference=r["n_det"] / n_full,
+                  e_minus_ref_mEh=1e3 * (r["energy"] - ref["energy"]), iters=r["iters"],
+                  time_s=r["time_s"], status=r["status"]) for r in rows]
+    log(f"selection {args.selection_workload}: reference E {ref['energy']:.8f} "
+        f"({n_full} determinants); " + "; ".join(
+            f"delta {t['delta']:g}: {t['n_det']} dets, {t['e_minus_ref_mEh']:.3f} mEh"
+            for t in table))
+    return {
+        "workload": args.selection_workload,
+        "reference": dict(n_det=n_full, energy=ref["energy"], resid=ref["resid_norm"],
+                          iters=ref["iters"], sector=ref["sector"]),
+        "rows": table,
+        "coef_histogram": dict(log10_bins="14 bins over [-14, 0)", counts=hist.tolist()),
+        "wall_s": time.perf_counter() - t0,
+    }
 
 
 def roofline_of(T, ctx, k64, workload):
@@ -663,6 +706,9 @@ def main():
         tb[spec] = tbsci_leg(T, torch, W, spec, args.extra_steps, min(args.warmup, 3))
     if tb:
         result["tbsci_spaces"] = tb
+
+    if args.selection_workload:
+        result["selection"] = selection_leg(T, W, args)
 
     if args.davidson_workload:
         dv, dprob, dctx, eig = davidson_leg(T, torch, W, args)

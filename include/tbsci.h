@@ -149,6 +149,39 @@ int tbsci_get_dets(const tbsci_ctx *ctx, int64_t *row_off_host, int32_t *beta_id
  */
 int tbsci_set_symmetry(tbsci_ctx *ctx, const int32_t *orb_irrep, int32_t target_irrep);
 
+/*
+ * String weights of a CI vector (Sec. III.B: the weight of an alpha or beta
+ * string is the sum of the squared coefficients over the determinants that
+ * contain it).  C_dev: device FP64 vector of the context's space (TPB
+ * [l_alpha][l_beta], or compact for a TBSCI space); w_alpha_dev /
+ * w_beta_dev: device FP64 outputs of l_alpha / l_beta entries.  Fixed-order
+ * reductions: the result does not depend on the launch.  Synchronous.
+ */
+int tbsci_string_weights(tbsci_ctx *ctx, const double *C_dev, double *w_alpha_dev,
+                         double *w_beta_dev, void *stream);
+
+/*
+ * Weight-threshold selection (Sec. III.B: strings are ranked by weight and
+ * kept when their weight exceeds delta times that of the Hartree-Fock
+ * string).  w_dev: device weights of one spin (tbsci_string_weights);
+ * ref_string: the reference string, which must be in the list and is always
+ * kept.  out_host receives the kept strings, heaviest first (ties: smaller
+ * string first), *n_out their number; out_host needs room for l entries of
+ * that spin.  Synchronous.
+ */
+int tbsci_select_strings(tbsci_ctx *ctx, int spin, const double *w_dev, double delta,
+                         uint64_t ref_string, uint64_t *out_host, int64_t *n_out, void *stream);
+
+/*
+ * Histogram of the coefficient magnitudes of a CI vector of the context's
+ * space (Sec. III.B, the coefficient distributions of the wavefunctions):
+ * counts_host[b] = number of coefficients with log10 |c| in bin b of nbins
+ * equal bins over [log10_lo, log10_hi); smaller magnitudes and zeros count in
+ * bin 0, larger ones in bin nbins-1.  nbins 1..4096.  Synchronous.
+ */
+int tbsci_coef_histogram(tbsci_ctx *ctx, const double *C_dev, double log10_lo, double log10_hi,
+                         int nbins, int64_t *counts_host, void *stream);
+
 /* Irrep of every string of one spin (spin 0 = alpha), computed on the
  * device, to a host buffer of l entries.  TBSCI_E_STATE before
  * tbsci_set_symmetry. */

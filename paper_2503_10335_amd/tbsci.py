@@ -95,6 +95,9 @@ def load():
         "tbsci_get_dets": (c_int, [P, P, P]),
         "tbsci_set_symmetry": (c_int, [P, P, c_int]),
         "tbsci_string_irreps": (c_int, [P, c_int, P]),
+        "tbsci_string_weights": (c_int, [P, P, P, P, P]),
+        "tbsci_select_strings": (c_int, [P, c_int, P, c_dbl, ctypes.c_uint64, P, P, P]),
+        "tbsci_coef_histogram": (c_int, [P, P, c_dbl, c_dbl, c_int, P, P]),
         "tbsci_sigma": (c_int, [P, P, P, c_int, P]),
         "tbsci_sigma_terms": (c_int, [P, P, P, c_int, c_int, P]),
         "tbsci_sigma_noalloc": (c_int, [P, P, P, c_int, P]),
@@ -468,6 +471,32 @@ class Context:
     def string_irreps(self, spin):
         return tbsci_string_irreps(self._ctx, spin, self.l_alpha if spin == 0 else self.l_beta)
 
+    def string_weights(self, C, stream=None):
+        """(w_alpha, w_beta) device FP64 tensors of a CI vector's string weights."""
+        wa = torch.empty(self.l_alpha, dtype=torch.float64, device=self._dev())
+        wb = torch.empty(self.l_beta, dtype=torch.float64, device=self._dev())
+        _check(load().tbsci_string_weights(self._ctx, ctypes.c_void_p(C.data_ptr()),
+                                           ctypes.c_void_p(wa.data_ptr()),
+                                           ctypes.c_void_p(wb.data_ptr()), _stream(stream)))
+        return wa, wb
+
+    def select_strings(self, spin, w, delta, ref_string, stream=None):
+        """Strings of one spin whose weight exceeds delta x the reference's."""
+        l = self.l_alpha if spin == 0 else self.l_beta
+        out = np.zeros(max(l, 1), dtype=np.uint64)
+        n = ctypes.c_int64()
+        _check(load().tbsci_select_strings(self._ctx, int(spin), ctypes.c_void_p(w.data_ptr()),
+                                           float(delta), ctypes.c_uint64(int(ref_string)),
+                                           _np_ptr(out), ctypes.byref(n), _stream(stream)))
+        return out[:n.value].copy()
+
+    def coef_histogram(self, C, log10_lo=-12.0, log10_hi=0.0, nbins=24, stream=None):
+        counts = np.zeros(nbins, dtype=np.int64)
+        _check(load().tbsci_coef_histogram(self._ctx, ctypes.c_void_p(C.data_ptr()),
+                                           float(log10_lo), float(log10_hi), int(nbins),
+                                           _np_ptr(counts), _stream(stream)))
+        return counts
+
     def _shape(self):
         return (self.n_det,) if getattr(self, "compact", False) else (self.l_alpha, self.l_beta)
 
@@ -525,6 +554,48 @@ class Context:
 
     def get_list(self, spin, kind):
         return tbsci_get_list(self._ctx, spin, kind, self.l_alpha if spin == 0 else self.l_beta)
+
+
+def selection_loop(prob, deltas, ref_string=None, symmetry=None, device=0, **davidson_opts):
+    """String-weight selection (Sec. III.B): solve the problem's space for a
+    reference vector, weigh its strings, and for each relative threshold
+    delta solve the TPB space of the strings kept (all of its determinants,
+    or those of the target irrep when `symmetry` = (orbital irreps, target)).
+    The reference string defaults to the lowest orbitals occupied.  Returns
+    the reference solve and one dict per delta (strings kept per spin,
+    determinants, energy, iterations).  Argument marshalling and bookkeeping
+    only: the solves, weights and thresholds run in the library."""
+    if ref_string is None:
+        ref_string = sum(1 << q for q in range(prob.n_alpha))
+        ref_b = sum(1 << q for q in range(prob.n_beta))
+    else:
+        ref_b = ref_string
+    ctx = Context.from_problem(prob, device)
+    if symmetry is not None:
+        ctx.set_symmetry(*symmetry)
+    ref, X = ctx.davidson(**davidson_opts)
+    wa, wb = ctx.string_weights(X)
+    out = []
+    for d in deltas:
+        a = ctx.select_strings(0, wa, d, ref_string)
+        b = ctx.select_strings(1, wb, d, ref_b)
+        if prob.n_alpha == prob.n_beta and np.array_equal(prob.alpha, prob.beta):
+            # one list for both spins (the union, heaviest first by alpha weight)
+            seen = set(map(int, a))
+            a = np.concatenate([a, np.array([x for x in b if int(x) not in seen],
+                                            dtype=np.uint64)])
+            b = a.copy()
+        sub = Context(prob.M, prob.n_alpha, prob.n_beta, prob.h, prob.eri, a, b, device)
+        if symmetry is not None:
+            sub.set_symmetry(*symmetry)
+        info, _ = sub.davidson(want_vector=False, **davidson_opts)
+        out.append(dict(delta=d, n_alpha_strings=len(a), n_beta_strings=len(b),
+                        n_det=sub.n_det, energy=info["energy"], status=info["status"],
+                        iters=info["iters"], sector=info["sector"],
+                        time_s=info["t_total_s"]))
+        sub.close()
+    ctx.close()
+    return ref, X, out
 
 
 def sigma_batch(contexts, Cs, precision=TBSCI_FP64, stream=None):

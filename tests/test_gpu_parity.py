@@ -199,6 +199,9 @@ def test_davidson_fp64_vs_dense(env, name):
     if sp.n_det <= 6000:
         e_ref, _ = O.lowest_eigpair_dense(sp.dense_h())
     else:
+        # residual 1e-9: the energy error is ~|r|^2/gap ~ 1e-16 Eh, far
+        # below the 1e-8 Eh of the check, while 1e-10 takes the oracle's
+        # plain collapse restart thousands of iterations on this space
         res = O.davidson(sp.sigma, sp.diag(), tol=1e-9, n_max=12)
         assert res["converged"]
         e_ref = res["energy"]

@@ -391,9 +391,11 @@ __device__ __forceinline__ auto pick4(const V4 &v, int r) {
 
 // Where the output row accumulates: kRowF64, a whole FP64 row in LDS;
 // kRowSplit, an FP64 row in LDS for the first nrow beta strings, the links
-// to strings beyond nrow going to sigma through global atomics; kRowT, a
+// to strings beyond nrow going to sigma through global atomics; kRowSplitT,
+// the same with a row of type T (an FP32 sigma keeps twice as many entries
+// in LDS); kRowT, a
 // whole row of type T in LDS
-enum { kRowF64 = 0, kRowT = 1, kRowSplit = 2 };
+enum { kRowF64 = 0, kRowT = 1, kRowSplit = 2, kRowSplitT = 3 };
 
 constexpr size_t kLdsMax = 160 * 1024;
 
@@ -623,8 +625,9 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
                                              const T *__restrict__ V, const T *__restrict__ C,
                                              T *__restrict__ S) {
     using M = Mfma<T>;
-    using R = typename std::conditional<ROW == kRowT, T, double>::type;
-    const int64_t nrow = ROW == kRowSplit ? L.nrow : lb;
+    using R = typename std::conditional<ROW == kRowT || ROW == kRowSplitT, T, double>::type;
+    constexpr bool kSplit = ROW == kRowSplit || ROW == kRowSplitT;
+    const int64_t nrow = kSplit ? L.nrow : lb;
     extern __shared__ __align__(16) unsigned char smem[];
     R *row = (R *)(smem + L.row);
     int32_t *aj = (int32_t *)(smem + L.aj);
@@ -740,7 +743,7 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
             auto put = [&](const Ent &e) {
                 T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
                 if ((e.o >> 12) & 1u) v = -v;
-                if (ROW != kRowSplit || e.j < nrow)
+                if (!kSplit || e.j < nrow)
                     atomicAdd(&row[e.j], (R)v);
                 else
                     atomicAdd(&S[I * lb + e.j], v);
@@ -898,14 +901,23 @@ void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
     SlabgLds L = slabg_lds(B.l, ks, 8);
     if (L.nrow < B.l) {
         row = kRowSplit;
-        if (sizeof(T) < 8 && slabg_lds(B.l, ks, sizeof(T), B.l).total <= kLdsMax) {
-            row = kRowT;
-            L = slabg_lds(B.l, ks, sizeof(T), B.l);
+        if (sizeof(T) < 8) {
+            // an FP32 sigma keeps a whole FP32 row when that fits, else the
+            // longer FP32 part of a split row
+            const SlabgLds Lt = slabg_lds(B.l, ks, sizeof(T), B.l);
+            if (Lt.total <= kLdsMax) {
+                row = kRowT;
+                L = Lt;
+            } else {
+                row = kRowSplitT;
+                L = slabg_lds(B.l, ks, sizeof(T));
+            }
         }
     }
-    auto f = row == kRowF64 ? k_ab_slabg<T, KS, kRowF64>
-             : row == kRowT ? k_ab_slabg<T, KS, kRowT>
-                            : k_ab_slabg<T, KS, kRowSplit>;
+    auto f = row == kRowF64      ? k_ab_slabg<T, KS, kRowF64>
+             : row == kRowT      ? k_ab_slabg<T, KS, kRowT>
+             : row == kRowSplitT ? k_ab_slabg<T, KS, kRowSplitT>
+                                 : k_ab_slabg<T, KS, kRowSplit>;
     if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
     f<<<(unsigned)A.l, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
                                                   B.g_ent, B.g_off, Vals<T>::V(c), C, S);

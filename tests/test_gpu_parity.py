@@ -402,15 +402,15 @@ def test_sigma_global_fragments_many_links(env):
     ctx.close()
 
 
-@pytest.mark.parametrize("shape", [(24, 18000), (16, 21000)])
+@pytest.mark.parametrize("shape", [(24, 18000), (16, 21000), (10, 45000)])
 def test_sigma_global_fragments_long_rows(env, shape):
-    """Beta lists too long for the slab kernel's LDS (an FP64 row of 18000 or
-    21000 strings plus FP64 fragments): FP64 sigma reads its fragments from
-    global memory, with the whole FP64 row in LDS (18000) or the row split
-    between LDS and global atomics (21000).  FP32 sigma: fragments in LDS
-    (18000; they are half the size) or from global memory with a whole FP32
-    row in LDS (21000).  Eight alpha rows, first and last included, against
-    the oracle."""
+    """Beta lists too long for the slab kernel's LDS (an FP64 row of 18000,
+    21000 or 45000 strings plus FP64 fragments): FP64 sigma reads its
+    fragments from global memory, with the whole FP64 row in LDS (18000) or
+    the row split between LDS and global atomics (21000, 45000).  FP32 sigma:
+    fragments in LDS (18000; they are half the size), or from global memory
+    with a whole FP32 row in LDS (21000) or a split FP32 row (45000).  Eight
+    alpha rows, first and last included, against the oracle."""
     T, O, torch = env
     la, lb = shape
     p = W.random_selection(18, 9, 9, la, lb, seed=43)

@@ -247,6 +247,9 @@ def parse():
     ap.add_argument("--davidson-storage", type=int, default=0,
                     help="0 auto, 1 full, 2 lean vector storage")
     ap.add_argument("--davidson-max-iter", type=int, default=600)
+    ap.add_argument("--davidson-subspace", type=int, default=-1,
+                    help="start the timed solves from a subspace of this many strings per spin "
+                         "(0: the library's default size; -1: from the smallest diagonal)")
     ap.add_argument("--no-davidson-ref", action="store_true",
                     help="skip the FP64 reference solve to |r| <= 1e-6 (for spaces where it "
                          "takes too long); the mixed energy is then compared with the FP64 one")
@@ -491,6 +494,8 @@ def davidson_leg(T, torch, W, args):
     ref = None
     if not args.no_davidson_ref:
         ref, _ = ctx.davidson(tol_resid=1e-6, want_vector=False, **kw)
+    if args.davidson_subspace >= 0:
+        kw["subspace_guess"] = args.davidson_subspace
         log(f"davidson reference {ref['energy']:.10f} ({ref['iters']} builds)")
     d64, X = ctx.davidson(tol_resid=args.davidson_tol, **kw)
     eig_host = {"fp64": (d64["energy"], X)}
@@ -519,6 +524,9 @@ def davidson_leg(T, torch, W, args):
         "workload": name,
         "stop": f"FP64 residual norm <= {args.davidson_tol:g} (energy error ~ |r|^2/gap)",
         "n_max": args.davidson_n_max,
+        "start": ("smallest diagonal element" if args.davidson_subspace < 0 else
+                  f"subspace of {args.davidson_subspace or 'the default number of'} strings "
+                  f"per spin, solved first"),
         "sectors": "both spin-flip sectors, lowest returned" if args.davidson_sector == 0
         else f"sector {args.davidson_sector} only",
         "e_ref": e_ref, "ref_resid": ref["resid_norm"] if ref else None,

@@ -235,6 +235,9 @@ int tbsci_diag(tbsci_ctx *ctx, double *diag_dev, void *stream);
 /* Davidson start vector */
 #define TBSCI_GUESS_DIAG 0 /* unit vector(s) on the smallest diagonal element          */
 #define TBSCI_GUESS_USER 1 /* the caller's vector guess_dev                             */
+#define TBSCI_GUESS_SUBSPACE 2 /* the ground state of the space of the guess_strings
+                              strings of each spin with the smallest same-spin diagonal,
+                              solved first (per spin-flip sector) and extended by zeros */
 /* Davidson vector storage */
 #define TBSCI_STORE_AUTO 0 /* FULL when it fits in 90% of the free device memory       */
 #define TBSCI_STORE_FULL 1 /* 2 n_max + 7 FP64 vectors (restart keeps two directions)  */
@@ -249,6 +252,8 @@ typedef struct {
                                  both spin-flip sectors, +1 = C^T = C only, -1 = C^T = -C
                                  only (ignored for other spaces and for a user guess)   */
     int storage;              /* TBSCI_STORE_AUTO, _FULL or _LEAN                        */
+    int guess_strings;        /* TBSCI_GUESS_SUBSPACE: strings per spin of the subspace
+                                 (0: a fifth of each list, at least 50)                 */
     double tol_resid;         /* stop when the FP64 residual norm <= tol_resid          */
     double tol_energy;        /* and |E_k - E_{k-1}| <= tol_energy (0 disables)         */
     double fp32_switch_resid; /* mixed: leave the FP32 phase below this residual        */
@@ -273,8 +278,8 @@ typedef struct {
 } tbsci_davidson_info;
 
 /* Defaults: n_max 8, max_iter 200, FP64, TBSCI_GUESS_DIAG, sector 0,
- * TBSCI_STORE_AUTO, tol_resid 1e-6, tol_energy 0, fp32_switch_resid 1e-4,
- * precond_floor 1e-8. */
+ * TBSCI_STORE_AUTO, guess_strings 0, tol_resid 1e-6, tol_energy 0,
+ * fp32_switch_resid 1e-4, precond_floor 1e-8. */
 void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
 
 /*
@@ -302,7 +307,14 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *opts);
  *   opts      host, NULL for defaults
  *   guess_dev device double [l_alpha][l_beta]: required with
  *             TBSCI_GUESS_USER (no sector is imposed then), must be NULL
- *             with TBSCI_GUESS_DIAG: the start is the unit vector on the
+ *             otherwise.  TBSCI_GUESS_SUBSPACE (whole TPB spaces only): the
+ *             library first solves, in FP64 to a residual of
+ *             max(tol_resid, 1e-3), the TPB space of the guess_strings
+ *             strings of each spin with the smallest same-spin diagonal
+ *             (the same strings for both spins when the lists are
+ *             identical), once per spin-flip sector, and starts each sector
+ *             from that solution extended by zeros (a P-space start;
+ *             info.t_total_s includes it).  TBSCI_GUESS_DIAG: the start is the unit vector on the
  *             smallest diagonal element (first in row-major order on ties);
  *             in a flip-symmetric space, (|I J> + |J I>)/sqrt 2 for an
  *             open-shell |I J> in the symmetric sector, and

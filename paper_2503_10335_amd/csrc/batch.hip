@@ -629,7 +629,7 @@ size_t BatchEngine::slot_bytes(int64_t n, const tbsci_davidson_opts &o, bool lea
     return b;
 }
 
-BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o, bool guess) {
+BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o, bool guess, bool split) {
     const int64_t n = c->sp[0].l * c->sp[1].l;
     bool lean = o.storage == TBSCI_STORE_LEAN;
     if (o.storage == TBSCI_STORE_AUTO) {
@@ -674,6 +674,15 @@ BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o, bool gue
             s->f32b = (float *)get(4 * (size_t)s->n);
         }
         s->G.assign((size_t)o.n_max * o.n_max, 0.0);
+        if (split && npass == 2) {  // the antisymmetric sector in a slot of its own
+            tbsci_davidson_opts ot = o;
+            ot.sector = -1;
+            ot.storage = lean ? TBSCI_STORE_LEAN : TBSCI_STORE_FULL;
+            s->twin = make_slot(c, ot, false, false);
+            s->twin->primary = s;
+            s->npass = 1;
+            s->bytes += s->twin->bytes;
+        }
     } catch (...) {
         free_slot(s);
         throw;
@@ -683,12 +692,19 @@ BatchSlot *BatchEngine::make_slot(Ctx *c, const tbsci_davidson_opts &o, bool gue
 
 void BatchEngine::free_slot(BatchSlot *s) {
     if (!s) return;
+    if (s->twin) free_slot(s->twin);
     for (double *p : s->all)
         if (p) (void)hipFree(p);
     delete s;
 }
 
 void BatchEngine::add(BatchSlot *s) {
+    if (s->twin) {
+        if (free_rows_.size() < 2) throw Error(TBSCI_E_STATE, "batch is full");
+        s->twin->user = s->user;
+        add(s->twin);
+    }
+    s->held = false;
     if (free_rows_.empty()) throw Error(TBSCI_E_STATE, "batch is full");
     s->row = free_rows_.back();
     free_rows_.pop_back();
@@ -712,13 +728,18 @@ std::vector<BatchSlot *> BatchEngine::take_done() {
 }
 
 std::vector<BatchSlot *> BatchEngine::drain() {
-    std::vector<BatchSlot *> v;
+    std::vector<BatchSlot *> v, out;
     v.swap(act_);
     for (BatchSlot *s : v) {
         free_rows_.push_back(s->row);
         s->row = -1;
     }
-    return v;
+    // report each solve once, by its primary slot (a held partner included)
+    for (BatchSlot *s : v) {
+        BatchSlot *p = s->primary ? s->primary : s;
+        if (std::find(out.begin(), out.end(), p) == out.end()) out.push_back(p);
+    }
+    return out;
 }
 
 void BatchEngine::plan(BatchSlot &s, Stage &S) {
@@ -820,7 +841,8 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
             dg.o0 = s.diag;
             S.ops[O_DIAG].push_back(dg);
         }
-        if (s.phase == BatchSlot::kStart && !s.guess) {
+        const double *g = s.guess ? s.guess : s.pass_guess[std::min(s.pass, 1)];
+        if (s.phase == BatchSlot::kStart && !g) {
             P.V0 = take(s.vfree);
             VDesc f = base();
             f.o0 = P.V0;
@@ -839,7 +861,7 @@ void BatchEngine::plan(BatchSlot &s, Stage &S) {
             P.V0 = take(s.vfree);
             VDesc cp = base();
             cp.o0 = P.V0;
-            cp.in = s.guess;
+            cp.in = g;
             S.ops[O_GCOPY].push_back(cp);
             dots(O_GN_D, {P.V0}, P.V0, sGN);
             scale(O_GN_S, P.V0, nullptr, sGN, -1, 0.0);
@@ -1099,13 +1121,45 @@ bool BatchEngine::tick() {
         if (s->phase == BatchSlot::kDone) {
             free_rows_.push_back(s->row);
             s->row = -1;
-            done_.push_back(s);
+            BatchSlot *partner = s->twin ? s->twin : s->primary;
+            if (!partner) {
+                done_.push_back(s);
+            } else if (partner->held) {  // both sectors done: one result
+                BatchSlot *p = s->primary ? s->primary : s;
+                merge_twins(*p);
+                done_.push_back(p);
+            } else {
+                s->held = true;
+            }
         } else {
             still.push_back(s);
         }
     }
     act_.swap(still);
     return true;
+}
+
+// Result of a split two-sector solve from its two slots: the lower state,
+// the other sector's energy, iterations of both, wall time of the longer.
+void BatchEngine::merge_twins(BatchSlot &p) {
+    BatchSlot &q = *p.twin;
+    const bool q_low = q.info.energy < p.info.energy;
+    const tbsci_davidson_info a = p.info, b = q.info;
+    const tbsci_davidson_info &lo = q_low ? b : a, &hi = q_low ? a : b;
+    p.info = lo;
+    p.info.energy_other = hi.energy;
+    p.info.iters = a.iters + b.iters;
+    p.info.iters_fp32 = a.iters_fp32 + b.iters_fp32;
+    p.info.iters_fp64 = a.iters_fp64 + b.iters_fp64;
+    p.info.converged = (a.converged && b.converged) ? 1 : 0;
+    p.info.t_total_s = std::max(a.t_total_s, b.t_total_s);
+    p.info.t_sigma_s = std::max(a.t_sigma_s, b.t_sigma_s);
+    int st = p.status;
+    if (q.status != TBSCI_OK && q.status != TBSCI_E_NOTCONV) st = q.status;
+    else if (st == TBSCI_OK && q.status != TBSCI_OK) st = q.status;
+    p.status = st;
+    if (st == TBSCI_E_INVAL) p.msg = q.status == TBSCI_E_INVAL ? q.msg : p.msg;
+    p.held = q.held = false;
 }
 
 // A pass has ended with Ritz vector x: one more round (kFinish) checks its
@@ -1201,7 +1255,8 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     };
 
     if (s.phase == BatchSlot::kStart || s.phase == BatchSlot::kHandover) {
-        if (s.phase == BatchSlot::kStart && s.guess && !(r[sGN] > 0.0)) {
+        const bool had_guess = s.guess || s.pass_guess[std::min(s.pass, 1)];
+        if (s.phase == BatchSlot::kStart && had_guess && !(r[sGN] > 0.0)) {
             release_v(P.V0);
             release_w(P.W0);
             s.status = TBSCI_E_INVAL;
@@ -1318,12 +1373,148 @@ void BatchEngine::commit(BatchSlot &s, const double *r, double t_sig) {
     s.k = kk + 1;
 }
 
+namespace {
+
+// G[ma[i]][mb[j]] = X[i][j] for the ka x kb subspace vector X (G zeroed)
+__global__ __launch_bounds__(kB) void k_embed(int64_t ka, int64_t kb, int64_t lb,
+                                              const int32_t *__restrict__ ma,
+                                              const int32_t *__restrict__ mb,
+                                              const double *__restrict__ X,
+                                              double *__restrict__ G) {
+    const int64_t n = ka * kb;
+    for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kB) {
+        const int64_t i = t / kb, j = t - i * kb;
+        G[(int64_t)ma[i] * lb + mb[j]] = X[t];
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_zero64(int64_t n, double *__restrict__ o) {
+    for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kB)
+        o[t] = 0.0;
+}
+
+template <typename T>
+std::vector<T> to_host(const T *d, size_t n) {
+    std::vector<T> h(n);
+    TB_HIP(hipMemcpy(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost));
+    return h;
+}
+
+// Start vectors of the passes of a solve from a subspace (a P-space
+// start): the k strings of each spin with the smallest same-spin diagonal
+// (the same strings for both spins of identical lists), that space solved
+// in FP64 per sector, each solution extended by zeros.  Returns the device
+// vectors (one per pass) and adds the time spent to *secs.
+std::vector<double *> subspace_guesses(Ctx &c, const tbsci_davidson_opts &o,
+                                       const std::vector<int> &sectors, hipStream_t st,
+                                       double *secs) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<double *> out;
+    Ctx *sub = nullptr;
+    int32_t *dmap = nullptr;
+    double *X = nullptr;
+    try {
+        const int M = c.M;
+        const int64_t la = c.sp[0].l, lb = c.sp[1].l;
+        auto pick = [&](const Spin &sp) {
+            int64_t k = o.guess_strings > 0 ? (int64_t)o.guess_strings
+                                            : std::max<int64_t>((sp.l + 4) / 5, 50);
+            k = std::min(k, sp.l);
+            const std::vector<double> d = to_host(sp.dsame, (size_t)sp.l);
+            std::vector<int32_t> idx((size_t)sp.l);
+            for (int64_t i = 0; i < sp.l; ++i) idx[(size_t)i] = (int32_t)i;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int32_t a, int32_t b) { return d[(size_t)a] < d[(size_t)b]; });
+            idx.resize((size_t)k);
+            std::sort(idx.begin(), idx.end());  // keep the caller's order
+            return idx;
+        };
+        const std::vector<int32_t> ia = pick(c.sp[0]);
+        const std::vector<int32_t> ib = c.flip ? ia : pick(c.sp[1]);
+        const std::vector<uint64_t> sa = to_host(c.sp[0].str, (size_t)la);
+        const std::vector<uint64_t> sb = to_host(c.sp[1].str, (size_t)lb);
+        std::vector<uint64_t> ua, ub;
+        for (int32_t i : ia) ua.push_back(sa[(size_t)i]);
+        for (int32_t i : ib) ub.push_back(sb[(size_t)i]);
+        const std::vector<double> h = to_host(c.h, (size_t)M * M);
+        const std::vector<double> eri = to_host(c.eri, (size_t)M * M * M * M);
+        sub = create_ctx(M, c.sp[0].n, c.sp[1].n, h.data(), eri.data(), ua.data(),
+                         (int64_t)ua.size(), ub.data(), (int64_t)ub.size(), c.device);
+        const int64_t ka = (int64_t)ua.size(), kb = (int64_t)ub.size();
+        TB_HIP(hipMalloc((void **)&dmap, sizeof(int32_t) * (ka + kb)));
+        TB_HIP(hipMemcpy(dmap, ia.data(), sizeof(int32_t) * ka, hipMemcpyHostToDevice));
+        TB_HIP(hipMemcpy(dmap + ka, ib.data(), sizeof(int32_t) * kb, hipMemcpyHostToDevice));
+        TB_HIP(hipMalloc((void **)&X, sizeof(double) * ka * kb));
+        for (int sec : sectors) {
+            tbsci_davidson_opts os = o;
+            os.precision = TBSCI_FP64;
+            os.guess_kind = TBSCI_GUESS_DIAG;
+            os.storage = TBSCI_STORE_FULL;
+            os.sector = sec;
+            os.tol_resid = std::max(o.tol_resid, 1e-3);
+            os.tol_energy = 0.0;
+            tbsci_davidson_info si{};
+            (void)solve_one(*sub, os, nullptr, X, si, st);
+            double *G = nullptr;
+            TB_HIP(hipMalloc((void **)&G, sizeof(double) * la * lb));
+            out.push_back(G);
+            const int64_t n = la * lb, m = ka * kb;
+            k_zero64<<<(unsigned)std::min<int64_t>((n + kB - 1) / kB, 16384), kB, 0, st>>>(n, G);
+            k_embed<<<(unsigned)std::min<int64_t>((m + kB - 1) / kB, 16384), kB, 0, st>>>(
+                ka, kb, lb, dmap, dmap + ka, X, G);
+            TB_HIP(hipGetLastError());
+        }
+        TB_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        for (double *g : out) (void)hipFree(g);
+        if (X) (void)hipFree(X);
+        if (dmap) (void)hipFree(dmap);
+        destroy_ctx(sub);
+        throw;
+    }
+    (void)hipFree(X);
+    (void)hipFree(dmap);
+    destroy_ctx(sub);
+    *secs += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return out;
+}
+
+}  // namespace
+
 int solve_one(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double *out,
               tbsci_davidson_info &info, hipStream_t st, const std::atomic<bool> *abort) {
     reserve_sigma_workspace(c);
+    // a subspace start: one start vector per sector the solve will run
+    std::vector<double *> pg;
+    double sub_s = 0.0;
+    if (o.guess_kind == TBSCI_GUESS_SUBSPACE && !guess) {
+        if (c.dets) throw Error(TBSCI_E_INVAL, "subspace starts need the whole TPB space");
+        std::vector<int> secs;
+        if (!c.flip) {
+            secs = {0};
+        } else if (o.sector != 0) {
+            secs = {o.sector};
+        } else {
+            secs = {1};
+            if (c.sp[0].l >= 2) secs.push_back(-1);
+        }
+        if (c.flip && o.sector == -1 && c.sp[0].l < 2)
+            throw Error(TBSCI_E_INVAL, "the antisymmetric sector of this space is empty");
+        pg = subspace_guesses(c, o, secs, st, &sub_s);
+    }
+    struct FreeG {
+        std::vector<double *> &v;
+        ~FreeG() {
+            for (double *g : v) (void)hipFree(g);
+        }
+    } free_g{pg};
     BatchSlot *s = BatchEngine::make_slot(&c, o, guess != nullptr);
     s->guess = guess;
     s->out = out;
+    for (size_t i = 0; i < pg.size() && i < 2; ++i) s->pass_guess[i] = pg[i];
     int rc = TBSCI_OK;
     try {
         BatchEngine eng(c.device, st);
@@ -1337,6 +1528,7 @@ int solve_one(Ctx &c, const tbsci_davidson_opts &o, const double *guess, double 
                 break;
             }
         info = s->info;
+        info.t_total_s += sub_s;
         if (aborted) {
             eng.drain();
             info.energy = s->theta;
@@ -1477,13 +1669,25 @@ int tbsci_davidson_batch(tbsci_ctx *const *ctxs, int n, const tbsci_davidson_opt
             eng.trace = tr && tr[0] && tr[0] != '0';
             for (int i = 0; i < n; ++i) {
                 reserve_sigma_workspace(*cs[i]);
-                slots.push_back(BatchEngine::make_slot(cs[i], os[i]));
+                slots.push_back(BatchEngine::make_slot(cs[i], os[i], false, true));
                 slots.back()->user = (void *)(intptr_t)i;
-                eng.add(slots.back());
             }
-            while (eng.tick()) {
+            // two-sector problems add two slots; the rest wait for room
+            size_t next = 0, running = 0;
+            std::vector<BatchSlot *> fin;
+            for (;;) {
+                while (next < slots.size() &&
+                       running + BatchEngine::slots_of(slots[next]) <= (size_t)kBatchMaxSlots) {
+                    running += BatchEngine::slots_of(slots[next]);
+                    eng.add(slots[next++]);
+                }
+                if (!eng.tick()) break;
+                for (BatchSlot *s : eng.take_done()) {
+                    running -= BatchEngine::slots_of(s);
+                    fin.push_back(s);
+                }
             }
-            for (BatchSlot *s : eng.take_done()) {
+            for (BatchSlot *s : fin) {
                 const int i = (int)(intptr_t)s->user;
                 infos[i] = s->info;
                 status[i] = s->status;

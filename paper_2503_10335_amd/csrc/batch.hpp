@@ -35,12 +35,22 @@ constexpr int kBatchMaxSlots = 64;
 struct BatchSlot {
     Ctx *c = nullptr;
     tbsci_davidson_opts o{};
-    const double *guess = nullptr;  // optional start vector (device)
+    const double *guess = nullptr;  // optional start vector (device); no sector imposed
+    // start vectors of the passes from a subspace solve (device, may be
+    // null); unlike `guess` they keep the pass's sector
+    const double *pass_guess[2] = {nullptr, nullptr};
     double *out = nullptr;          // optional eigenvector output (device)
     // spin-flip sector of the current pass: +1 (C^T = C), -1 (C^T = -C) or
     // 0 (none imposed); a two-sector solve runs pass 0 in +1, pass 1 in -1
     int sector = 0;
     int npass = 1, pass = 0;
+    // two-sector solves without an output vector can run their sectors at
+    // the same time: the primary slot (sector +1) owns a twin (sector -1)
+    // with its own vectors; the engine reports the primary once both are
+    // done, with the lower state
+    BatchSlot *twin = nullptr;
+    BatchSlot *primary = nullptr;  // set on the twin
+    bool held = false;             // finished, waiting for its partner
     bool lean = false;  // 2 n_max + 3 vectors: collapse restart, no stored diagonal
     int64_t n = 0;
     int nb = 1;    // blocks of this slot in grid-stride launches
@@ -107,8 +117,13 @@ class BatchEngine {
         return slot_bytes(n, o, o.storage == TBSCI_STORE_LEAN);
     }
     // allocate a slot for context c (any thread; allocation only); guess:
-    // whether a start vector will be given (no sector is imposed then)
-    static BatchSlot *make_slot(Ctx *c, const tbsci_davidson_opts &o, bool guess = false);
+    // whether a start vector will be given (no sector is imposed then);
+    // split: a two-sector solve gets a twin slot for its second sector
+    // (solves that write no output vector only)
+    static BatchSlot *make_slot(Ctx *c, const tbsci_davidson_opts &o, bool guess = false,
+                                bool split = false);
+    // slots a new solve adds to the engine (2 for a split solve)
+    static int slots_of(const BatchSlot *s) { return s->twin ? 2 : 1; }
     // free a slot's buffers (not its context); any thread, slot not active
     static void free_slot(BatchSlot *s);
 
@@ -132,6 +147,7 @@ class BatchEngine {
     void commit(BatchSlot &s, const double *r, double t_sig);
     void finish(BatchSlot &s, double *keep);
     void complete(BatchSlot &s);
+    void merge_twins(BatchSlot &p);
 
     int device_;
     hipStream_t st_;

@@ -59,8 +59,10 @@ void check_opts(const tbsci_davidson_opts &o) {
     if (!(o.tol_resid > 0.0) || !(o.precond_floor > 0.0) || o.tol_energy < 0.0 ||
         !(o.fp32_switch_resid > 0.0))
         throw Error(TBSCI_E_INVAL, "tolerances must be positive");
-    if (o.guess_kind != TBSCI_GUESS_DIAG && o.guess_kind != TBSCI_GUESS_USER)
-        throw Error(TBSCI_E_INVAL, "guess_kind must be TBSCI_GUESS_DIAG or TBSCI_GUESS_USER");
+    if (o.guess_kind != TBSCI_GUESS_DIAG && o.guess_kind != TBSCI_GUESS_USER &&
+        o.guess_kind != TBSCI_GUESS_SUBSPACE)
+        throw Error(TBSCI_E_INVAL, "guess_kind must be TBSCI_GUESS_DIAG, _USER or _SUBSPACE");
+    if (o.guess_strings < 0) throw Error(TBSCI_E_INVAL, "guess_strings must be >= 0");
     if (o.sector < -1 || o.sector > 1) throw Error(TBSCI_E_INVAL, "sector must be -1, 0 or 1");
     if (o.storage != TBSCI_STORE_AUTO && o.storage != TBSCI_STORE_FULL &&
         o.storage != TBSCI_STORE_LEAN)
@@ -81,6 +83,7 @@ void tbsci_davidson_default_opts(tbsci_davidson_opts *o) {
     o->guess_kind = TBSCI_GUESS_DIAG;
     o->sector = 0;
     o->storage = TBSCI_STORE_AUTO;
+    o->guess_strings = 0;
     o->tol_resid = 1e-6;
     o->tol_energy = 0.0;
     o->fp32_switch_resid = 1e-4;

@@ -53,8 +53,11 @@ struct Request {
 };
 
 size_t request_bound(const Request &r, bool batched) {
-    (void)batched;  // the batched and the solo solver hold the same state
-    const size_t solver = BatchEngine::slot_bytes(r.n_det, r.o);
+    // a batched request with identical lists solves its two spin-flip
+    // sectors in two slots at the same time; the solo solver runs them one
+    // after the other in one
+    const bool two = batched && r.na == r.nb && r.a == r.b && r.a.size() > 1 && r.o.sector == 0;
+    const size_t solver = BatchEngine::slot_bytes(r.n_det, r.o) * (two ? 2 : 1);
     return ctx_bytes_bound(r.M, r.na, r.nb, (int64_t)r.a.size(), (int64_t)r.b.size()) + solver;
 }
 
@@ -151,7 +154,7 @@ struct Server {
                 reserve_sigma_workspace(*r->ctx);
                 size_t held = ctx_bytes(*r->ctx);
                 if (r->batched) {
-                    r->slot = BatchEngine::make_slot(r->ctx, r->o);
+                    r->slot = BatchEngine::make_slot(r->ctx, r->o, false, true);
                     r->slot->user = r;
                     held += r->slot->bytes;
                 } else {
@@ -207,7 +210,9 @@ struct Server {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_eng.wait(lk, [&] { return stop || !ready_batch.empty() || e->active() > 0; });
                 if (stop) break;
-                while (!ready_batch.empty() && e->active() < (size_t)kBatchMaxSlots) {
+                while (!ready_batch.empty() &&
+                       e->active() + BatchEngine::slots_of(ready_batch.front()->slot) <=
+                           (size_t)kBatchMaxSlots) {
                     e->add(ready_batch.front()->slot);
                     ready_batch.pop_front();
                     ++running_batched;

@@ -23,6 +23,7 @@
 //   alpha sweep   : sparse rows of A_a times rows of C, one XCD per column
 //                   panel so each XCD's L2 holds its panel of C;
 //   beta sweep    : the same kernel on C^T, then a transpose-add.
+#include <algorithm>
 #include <vector>
 #include <type_traits>
 
@@ -1147,14 +1148,19 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
 void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, int n,
                         int precision, TableArena &ar, hipStream_t st) {
     // problems whose beta sweep runs in more than one block take their own
-    // launches; the others share them
+    // launches; the others share them.  A context that appears again (the
+    // two spin-flip sectors of one problem) shares its beta-sweep workspace,
+    // so its later appearances run after the shared launches, in stream order
     std::vector<Ctx *> gc;
     std::vector<const void *> gC;
     std::vector<void *> gS;
+    std::vector<int> later;
     for (int i = 0; i < n; ++i) {
         const int64_t la = ctx[i]->sp[0].l, lb = ctx[i]->sp[1].l;
         if (n == 1 || beta_block_rows(la, lb, kWorkCap) < la) {
             launch_sigma(*ctx[i], C[i], S[i], precision, st);
+        } else if (std::find(gc.begin(), gc.end(), ctx[i]) != gc.end()) {
+            later.push_back(i);
         } else {
             gc.push_back(ctx[i]);
             gC.push_back(C[i]);
@@ -1172,6 +1178,7 @@ void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, i
             sigma_group_impl<float>(gc.data(), (const float *const *)gC.data(),
                                     (float *const *)gS.data(), m, ar, st);
     }
+    for (int i : later) launch_sigma(*ctx[i], C[i], S[i], precision, st);
 }
 
 void reserve_sigma_workspace(Ctx &c) { (void)ctx_workspace(c); }

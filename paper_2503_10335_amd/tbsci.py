@@ -40,6 +40,7 @@ class TbsciError(RuntimeError):
 
 TBSCI_GUESS_DIAG = 0
 TBSCI_GUESS_USER = 1
+TBSCI_GUESS_SUBSPACE = 2
 TBSCI_STORE_AUTO = 0
 TBSCI_STORE_FULL = 1
 TBSCI_STORE_LEAN = 2
@@ -48,6 +49,7 @@ TBSCI_STORE_LEAN = 2
 class DavidsonOpts(ctypes.Structure):
     _fields_ = [("n_max", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("guess_kind", ctypes.c_int), ("sector", ctypes.c_int), ("storage", ctypes.c_int),
+                ("guess_strings", ctypes.c_int),
                 ("tol_resid", ctypes.c_double), ("tol_energy", ctypes.c_double),
                 ("fp32_switch_resid", ctypes.c_double), ("precond_floor", ctypes.c_double)]
 
@@ -374,10 +376,11 @@ def tbsci_server_stats(srv):
 
 def make_opts(n_max=8, max_iter=200, precision=TBSCI_FP64, tol_resid=1e-6, tol_energy=0.0,
               fp32_switch_resid=1e-4, precond_floor=1e-8, sector=0, storage=TBSCI_STORE_AUTO,
-              guess_kind=TBSCI_GUESS_DIAG):
+              guess_kind=TBSCI_GUESS_DIAG, guess_strings=0):
     o = tbsci_davidson_default_opts()
     o.n_max, o.max_iter, o.precision = n_max, max_iter, precision
     o.guess_kind, o.sector, o.storage = guess_kind, sector, storage
+    o.guess_strings = guess_strings
     o.tol_resid, o.tol_energy = tol_resid, tol_energy
     o.fp32_switch_resid, o.precond_floor = fp32_switch_resid, precond_floor
     return o
@@ -531,10 +534,18 @@ class Context:
 
     def davidson(self, n_max=8, max_iter=200, precision=TBSCI_FP64, tol_resid=1e-6,
                  tol_energy=0.0, fp32_switch_resid=1e-4, precond_floor=1e-8, guess=None,
-                 want_vector=True, sector=0, storage=TBSCI_STORE_AUTO, stream=None):
+                 want_vector=True, sector=0, storage=TBSCI_STORE_AUTO, subspace_guess=None,
+                 stream=None):
+        """subspace_guess: None, or the strings per spin of a subspace solved
+        first for the start vector (0 for the library's default size)."""
+        if guess is not None:
+            kind, k = TBSCI_GUESS_USER, 0
+        elif subspace_guess is not None:
+            kind, k = TBSCI_GUESS_SUBSPACE, int(subspace_guess)
+        else:
+            kind, k = TBSCI_GUESS_DIAG, 0
         o = make_opts(n_max, max_iter, precision, tol_resid, tol_energy, fp32_switch_resid,
-                      precond_floor, sector, storage,
-                      TBSCI_GUESS_USER if guess is not None else TBSCI_GUESS_DIAG)
+                      precond_floor, sector, storage, kind, k)
         if guess is not None and (guess.dtype != torch.float64 or guess.numel() != self.n_det):
             raise ValueError("guess must be an FP64 device tensor of n_det elements")
         X = torch.empty(self._shape(), dtype=torch.float64,

@@ -319,6 +319,37 @@ def test_davidson_lean_storage(env, n_max):
         ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_davidson_subspace_start(env, prec):
+    """A start from the subspace of the strings with the smallest same-spin
+    diagonal (solved first, per spin-flip sector) reaches the same lowest
+    state as the diagonal start, against dense references over both sectors
+    (identical lists with an antisymmetric ground state, and independent
+    lists), with the sector kept."""
+    T, O, torch = env
+    pr = T.TBSCI_FP64 if prec == "fp64" else T.TBSCI_MIXED
+    tol_r, tol_e = (1e-8, 1e-8) if prec == "fp64" else (1e-5, 1e-6)
+    for p, k in ((W.make_problem("anti_gs", 8, 4, None, 100), 20),
+                 (PROBS["rand_m8_3_4"], 0)):
+        ref = O.lowest_by_flip_sector(O.Space.of(p))
+        ctx = T.Context.from_problem(p)
+        info, X = ctx.davidson(tol_resid=tol_r, max_iter=600, precision=pr, subspace_guess=k)
+        assert info["status"] == 0 and abs(info["energy"] - ref["lowest"]) < tol_e
+        if ref["sector"]:
+            assert info["sector"] == ref["sector"]
+            assert abs(info["energy_other"] - ref["sym"]) < tol_e
+            x = X.cpu().numpy()
+            assert np.abs(x - ref["sector"] * x.T).max() < 1e-9
+        ctx.close()
+    # TBSCI spaces do not take subspace starts
+    ctx = T.Context.from_problem(PROBS["rand_m8_3_4"])
+    ctx.set_dets(*W.dets_random(37, 53, 0.5, 3))
+    with pytest.raises(T.TbsciError) as ei:
+        ctx.davidson(subspace_guess=0)
+    assert ei.value.code == T.TBSCI_E_INVAL
+    ctx.close()
+
+
 def test_davidson_option_errors(env):
     """guess_kind must match the guess pointer; an empty antisymmetric
     sector (one string per spin) and out-of-range options are rejected."""

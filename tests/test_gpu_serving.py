@@ -261,3 +261,34 @@ def test_server_errors_and_cancel(env):
     for q in _serving_requests(12, 5):
         srv.submit(q, **OPTS)
     srv.close()
+
+
+def test_two_sector_slots_in_batch_and_server(env):
+    """Batched and served solves of identical-list problems run their two
+    spin-flip sectors in two slots at once and report one result: the lowest
+    state (here antisymmetric: M = 8, N = 4, every string, integral seed
+    100), the other sector's lowest as energy_other, the iterations of both;
+    equal to the single solver's result."""
+    T, O, torch = env
+    p = W.make_problem("anti_gs", 8, 4, None, 100)
+    ref = O.lowest_by_flip_sector(O.Space.of(p))
+    ctx = T.Context.from_problem(p)
+    other = T.Context.from_problem(W.random_selection(8, 3, 4, 37, 53, seed=11))
+    single, _ = ctx.davidson(tol_resid=1e-8, want_vector=False)
+    res = T.davidson_batch([ctx, other], tol_resid=1e-8)
+    r = res[0]
+    assert r["status"] == 0 and r["sector"] == -1
+    assert abs(r["energy"] - ref["lowest"]) < 1e-8
+    assert abs(r["energy_other"] - ref["sym"]) < 1e-8
+    assert abs(r["energy"] - single["energy"]) < 1e-10
+    assert r["iters"] >= 2 and res[1]["status"] == 0 and res[1]["sector"] == 0
+    srv = T.Server()
+    tk = srv.submit(p, tol_resid=1e-8)
+    while (d := srv.poll(tk)) is None:
+        time.sleep(0.01)
+    assert d["status"] == 0 and d["batched"] and d["sector"] == -1
+    assert abs(d["energy"] - ref["lowest"]) < 1e-8
+    assert abs(d["energy_other"] - ref["sym"]) < 1e-8
+    srv.close()
+    ctx.close()
+    other.close()

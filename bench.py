@@ -247,7 +247,7 @@ def parse():
     ap.add_argument("--davidson-storage", type=int, default=0,
                     help="0 auto, 1 full, 2 lean vector storage")
     ap.add_argument("--davidson-max-iter", type=int, default=600)
-    ap.add_argument("--davidson-subspace", type=int, default=-1,
+    ap.add_argument("--davidson-subspace", type=int, default=0,
                     help="start the timed solves from a subspace of this many strings per spin "
                          "(0: the library's default size; -1: from the smallest diagonal)")
     ap.add_argument("--no-davidson-ref", action="store_true",
@@ -494,9 +494,9 @@ def davidson_leg(T, torch, W, args):
     ref = None
     if not args.no_davidson_ref:
         ref, _ = ctx.davidson(tol_resid=1e-6, want_vector=False, **kw)
+        log(f"davidson reference {ref['energy']:.10f} ({ref['iters']} builds)")
     if args.davidson_subspace >= 0:
         kw["subspace_guess"] = args.davidson_subspace
-        log(f"davidson reference {ref['energy']:.10f} ({ref['iters']} builds)")
     d64, X = ctx.davidson(tol_resid=args.davidson_tol, **kw)
     eig_host = {"fp64": (d64["energy"], X)}
     log(f"davidson fp64 {d64['t_total_s']:.3f}s ({d64['iters']} builds) E {d64['energy']:.10f}")

@@ -227,6 +227,25 @@ int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int pr
                       int terms, void *stream);
 
 /*
+ * Reproducible sigma (the run-to-run and alone-versus-batched equality of
+ * the sigma build, Sec. II.B-C, for serving): enable != 0 makes every sigma
+ * of this context bitwise identical across runs and identical whether it
+ * is built alone (tbsci_sigma) or inside a batch (tbsci_sigma_batch, the
+ * batched Davidson).  The opposite-spin term then sums each output element
+ * in 64-bit fixed point -- a power-of-two scale, taken per call from
+ * max|C|, max|(pq|rs)| and the longest single-excitation lists so that no
+ * partial sum can overflow -- so the order of its atomic adds no longer
+ * matters; the same-spin sweeps run in one fixed order.  Rounding: each
+ * opposite-spin contribution is rounded to 2^-62 of that bound, below the
+ * FP64 parity tolerance for any C.  Opposite-spin rows must fit in LDS
+ * (l_beta up to about 20,000 strings, the global-fragment kernel's FP64
+ * row); longer rows fail with TBSCI_E_INVAL while the mode is on.
+ * Allocates 16 bytes on the first enable.  enable == 0 returns to the
+ * default (FP64 atomics, chunked and panel sweeps).
+ */
+int tbsci_set_deterministic(tbsci_ctx *ctx, int enable);
+
+/*
  * Diagonal H_KK of every determinant (Sec. II.C: the [0,0] category,
  * precomputed and stored), device double [l_alpha][l_beta], asynchronous.
  */

@@ -86,7 +86,7 @@ void destroy_ctx(Ctx *c) {
     timing_clear(*c);
     free_dets(*c);
     for (auto &s : c->sp) free_spin(s);
-    void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work};
+    void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work, c->det_buf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -247,6 +247,7 @@ Ctx *create_ctx(int M, int n_alpha, int n_beta, const double *h, const double *e
                             const size_t k = (size_t)fold_pair(p, q) * P + fold_pair(r, s);
                             V64[k] = v;
                             V32[k] = (float)v;
+                            c->maxV = std::max(c->maxV, std::fabs(v));
                         }
             hipStream_t st;
             TB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -451,6 +452,19 @@ int tbsci_timing_enable(tbsci_ctx *ctx, int enable) {
         Ctx *c = ctx_of(ctx);
         timing_clear(*c);
         c->timing = enable != 0;
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_set_deterministic(tbsci_ctx *ctx, int enable) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        Ctx *c = ctx_of(ctx);
+        if (enable && !c->det_buf) {
+            TB_HIP(hipSetDevice(c->device));
+            c->det_buf = dalloc<double>(2);
+        }
+        c->det = enable != 0;
         return TBSCI_OK;
     });
 }

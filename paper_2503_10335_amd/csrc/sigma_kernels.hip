@@ -432,6 +432,18 @@ inline SlabLds slab_lds(int64_t lb, int nmt, int nks, size_t sz) {
     return L;
 }
 
+// Deterministic accumulation of the output row: with det != null the row
+// holds 64-bit fixed-point values, each contribution v added as
+// round(v * scale) with integer atomics (associative, so the sum does not
+// depend on the order of the adds); scale = *det, a power of two chosen so
+// that no partial sum can leave the 63-bit range (k_det_scale).
+__device__ __forceinline__ unsigned long long to_fixed(double v, double scale) {
+    return (unsigned long long)__double2ll_rn(v * scale);
+}
+__device__ __forceinline__ double from_fixed(unsigned long long a, double scale) {
+    return (double)(long long)a / scale;
+}
+
 template <typename T, int KS>
 __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, int nmt,
                                             const SlabLds L, const int64_t *__restrict__ sa_ptr,
@@ -440,10 +452,12 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
                                             const Ent *__restrict__ sb_grp,
                                             const int32_t *__restrict__ sb_off,
                                             const T *__restrict__ V, const T *__restrict__ C,
-                                            T *__restrict__ S) {
+                                            T *__restrict__ S, const double *__restrict__ det) {
     using M = Mfma<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     double *row = (double *)(smem + L.row);
+    unsigned long long *rowi = (unsigned long long *)(smem + L.row);
+    const double dscale = det ? *det : 0.0;
     T *afr = (T *)(smem + L.a);
     int32_t *aj = (int32_t *)(smem + L.aj);
     int *ctr = (int *)(smem + L.ctr);
@@ -554,7 +568,10 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
             auto put = [&](const Ent &e) {
                 T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
                 if ((e.o >> 12) & 1u) v = -v;
-                atomicAdd(&row[e.j], (double)v);
+                if (det)
+                    atomicAdd(&rowi[e.j], to_fixed((double)v, dscale));
+                else
+                    atomicAdd(&row[e.j], (double)v);
             };
             if (h0) put(e0);
             if (h1) put(e1);
@@ -564,7 +581,12 @@ __device__ __forceinline__ void ab_slab_row(const int64_t I, int64_t lb, int P, 
         }
     }
     __syncthreads();
-    for (int64_t i = tid; i < lb; i += nthr) S[I * lb + i] = (T)((double)S[I * lb + i] + row[i]);
+    if (det)
+        for (int64_t i = tid; i < lb; i += nthr)
+            S[I * lb + i] = (T)((double)S[I * lb + i] + from_fixed(rowi[i], dscale));
+    else
+        for (int64_t i = tid; i < lb; i += nthr)
+            S[I * lb + i] = (T)((double)S[I * lb + i] + row[i]);
 }
 
 constexpr int kSlabBlock = 1024;
@@ -578,9 +600,10 @@ __global__ __launch_bounds__(kSlabBlock) void k_ab_slab(int64_t lb, int P, int n
                                                        const int32_t *__restrict__ sb_off,
                                                        const T *__restrict__ V,
                                                        const T *__restrict__ C,
-                                                       T *__restrict__ S) {
+                                                       T *__restrict__ S,
+                                                       const double *__restrict__ det) {
     ab_slab_row<T, KS>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off, V, C,
-                       S);
+                       S, det);
 }
 
 // Slab kernel with the A fragments read from global memory, for rows whose
@@ -624,13 +647,17 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
                                              const Ent *__restrict__ sb_grp,
                                              const int32_t *__restrict__ sb_off,
                                              const T *__restrict__ V, const T *__restrict__ C,
-                                             T *__restrict__ S) {
+                                             T *__restrict__ S, const double *__restrict__ det) {
     using M = Mfma<T>;
     using R = typename std::conditional<ROW == kRowT || ROW == kRowSplitT, T, double>::type;
     constexpr bool kSplit = ROW == kRowSplit || ROW == kRowSplitT;
     const int64_t nrow = kSplit ? L.nrow : lb;
     extern __shared__ __align__(16) unsigned char smem[];
     R *row = (R *)(smem + L.row);
+    // fixed-point row (det) only with a whole FP64 row in LDS
+    unsigned long long *rowi = (unsigned long long *)(smem + L.row);
+    const bool fixed = ROW == kRowF64 && det;
+    const double dscale = fixed ? *det : 0.0;
     int32_t *aj = (int32_t *)(smem + L.aj);
     int32_t *apq = (int32_t *)(smem + L.apq);
     int *ctr = (int *)(smem + L.ctr);
@@ -744,7 +771,9 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
             auto put = [&](const Ent &e) {
                 T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
                 if ((e.o >> 12) & 1u) v = -v;
-                if (!kSplit || e.j < nrow)
+                if (fixed)
+                    atomicAdd(&rowi[e.j], to_fixed((double)v, dscale));
+                else if (!kSplit || e.j < nrow)
                     atomicAdd(&row[e.j], (R)v);
                 else
                     atomicAdd(&S[I * lb + e.j], v);
@@ -757,7 +786,12 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
         }
     }
     __syncthreads();
-    for (int64_t i = tid; i < nrow; i += nthr) S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
+    if (fixed)
+        for (int64_t i = tid; i < nrow; i += nthr)
+            S[I * lb + i] = (T)((double)S[I * lb + i] + from_fixed(rowi[i], dscale));
+    else
+        for (int64_t i = tid; i < nrow; i += nthr)
+            S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
 }
 
 template <typename T, int KS, int ROW>
@@ -769,9 +803,10 @@ __global__ __launch_bounds__(kSlabBlock) void k_ab_slabg(int64_t lb, int P, int 
                                                         const int32_t *__restrict__ sb_off,
                                                         const T *__restrict__ V,
                                                         const T *__restrict__ C,
-                                                        T *__restrict__ S) {
+                                                        T *__restrict__ S,
+                                                        const double *__restrict__ det) {
     ab_slabg_row<T, KS, ROW>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off,
-                             V, C, S);
+                             V, C, S, det);
 }
 
 // one problem of a grouped slab launch: blocks [blk0, blk0 + l_alpha)
@@ -785,6 +820,7 @@ struct SlabDesc {
     const int32_t *sb_off;
     const void *V, *C;
     void *S;
+    const double *det;  // fixed-point scale of the problem (deterministic mode) or null
 };
 
 template <typename T, int KS>
@@ -792,7 +828,7 @@ __global__ __launch_bounds__(kSlabBlock) void g_ab_slab(const SlabDesc *__restri
                                                        int P, int nmt) {
     const SlabDesc e = d[find_desc(d, nd, blockIdx.x)];
     ab_slab_row<T, KS>(blockIdx.x - e.blk0, e.lb, P, nmt, e.L, e.sa_ptr, e.sa_ent, e.sb_ptr,
-                       e.sb_grp, e.sb_off, (const T *)e.V, (const T *)e.C, (T *)e.S);
+                       e.sb_grp, e.sb_off, (const T *)e.V, (const T *)e.C, (T *)e.S, e.det);
 }
 
 // ---------------------------------------------------------------- driver
@@ -832,13 +868,16 @@ void launch_zero(int64_t n, T *o, hipStream_t st) {
 // first one writes unless acc), so that the X rows an XCD gathers in a pass
 // stay in its L2.
 template <typename T>
-void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st) {
+void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, hipStream_t st,
+                      bool fixed_order = false) {
     const int64_t nrows = s.l;
     const int vec = sweep_vec_of<T>(ncols);
     // one launch, panels staged in LDS: FP64, and FP32 with 4 columns per
     // lane (16-byte row segments like FP64; with 2 columns per lane FP32
-    // measured faster with the plain sweep out of L2)
-    if (s.chunk == kPanelRows && (sizeof(T) == 8 || vec == 4)) {
+    // measured faster with the plain sweep out of L2).  fixed_order: one
+    // plain pass over the whole rows, the summation order of the grouped
+    // sweep (deterministic sigma, equal alone and in a batch)
+    if (!fixed_order && s.chunk == kPanelRows && (sizeof(T) == 8 || vec == 4)) {
         const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec);
         const int64_t nrb = (nrows + kPanelBlockRows - 1) / kPanelBlockRows;
         const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
@@ -854,7 +893,7 @@ void launch_row_sweep(const Spin &s, int64_t ncols, const T *X, T *Y, bool acc, 
     const int64_t ntiles = (ncols + 64 * vec - 1) / (64 * vec), nrb = (nrows + 3) / 4;
     const int64_t tpx = (ntiles + kXcd - 1) / kXcd;
     const unsigned grid = (unsigned)(kXcd * tpx * nrb);
-    const bool chunked = s.chunk == kSweepChunk && s.nch > 1;
+    const bool chunked = !fixed_order && s.chunk == kSweepChunk && s.nch > 1;
     const int nch = chunked ? s.nch : 1;
     for (int ch = 0; ch < nch; ++ch) {
         const bool a = acc || ch > 0;
@@ -915,13 +954,17 @@ void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
             }
         }
     }
+    if (c.det && row != kRowF64)
+        throw Error(TBSCI_E_INVAL, "deterministic sigma needs each FP64 output row in LDS "
+                                   "(l_beta too long)");
     auto f = row == kRowF64      ? k_ab_slabg<T, KS, kRowF64>
              : row == kRowT      ? k_ab_slabg<T, KS, kRowT>
              : row == kRowSplitT ? k_ab_slabg<T, KS, kRowSplitT>
                                  : k_ab_slabg<T, KS, kRowSplit>;
     if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
     f<<<(unsigned)A.l, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
-                                                  B.g_ent, B.g_off, Vals<T>::V(c), C, S);
+                                                  B.g_ent, B.g_off, Vals<T>::V(c), C, S,
+                                                  c.det ? c.det_buf + 1 : nullptr);
     TB_HIP(hipGetLastError());
 }
 
@@ -941,7 +984,8 @@ void launch_ab_slab(Ctx &c, const T *C, T *S, hipStream_t st) {
     auto f = k_ab_slab<T, KS>;
     if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
     f<<<(unsigned)A.l, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
-                                                  B.g_ent, B.g_off, Vals<T>::V(c), C, S);
+                                                  B.g_ent, B.g_off, Vals<T>::V(c), C, S,
+                                                  c.det ? c.det_buf + 1 : nullptr);
     TB_HIP(hipGetLastError());
 }
 
@@ -1002,6 +1046,40 @@ __global__ __launch_bounds__(kBlock) void k_ab_direct(int64_t lb, int64_t ncb, i
     S[I * lb + Ip] += acc;
 }
 
+// Deterministic mode: the fixed-point scale of one sigma's opposite-spin
+// row.  Every partial sum of an output element is bounded by
+// K_a K_b max|V| max|C| (K = longest single-link list of a spin); the scale
+// is the power of two that maps that bound just inside 2^62.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_det_absmax(int64_t n, const T *__restrict__ C,
+                                                       unsigned long long *__restrict__ out) {
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        m = fmax(m, fabs((double)C[i]));
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    // non-negative doubles order like their bit patterns
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_det_scale(double *__restrict__ buf, double bound_per_c) {
+    const double maxc = __longlong_as_double((long long)((unsigned long long *)buf)[0]);
+    const double b = bound_per_c * maxc;
+    int e = 0;
+    if (b > 0.0) (void)frexp(b, &e);  // b < 2^e
+    buf[1] = ldexp(1.0, 62 - e);
+}
+
+template <typename T>
+void det_scale(Ctx &c, const T *C, int64_t n, hipStream_t st) {
+    const double kb = (double)std::max(c.sp[0].max_s, 1) * (double)std::max(c.sp[1].max_s, 1);
+    launch_zero<double>(2, c.det_buf, st);
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
+    k_det_absmax<T><<<(unsigned)g, kBlock, 0, st>>>(n, C, (unsigned long long *)c.det_buf);
+    k_det_scale<<<1, 1, 0, st>>>(c.det_buf, kb * c.maxV);
+    TB_HIP(hipGetLastError());
+}
+
 // sigma with the beta sweep in blocks of rb alpha rows; work holds
 // 2 l_beta rb elements of type T (C^T and the sweep result of a block)
 template <typename T>
@@ -1016,7 +1094,7 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work,
 
     timing_mark(c, 0, prec, st);
     if (terms & 1)
-        launch_row_sweep<T>(A, lb, C, S, false, st);  // sigma = A_a C
+        launch_row_sweep<T>(A, lb, C, S, false, st, c.det);  // sigma = A_a C
     else
         launch_zero<T>(la * lb, S, st);
     timing_mark(c, 1, prec, st);
@@ -1026,11 +1104,12 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work,
         for (int64_t r0 = 0; r0 < la; r0 += rb) {
             const int64_t nr = std::min(rb, la - r0);
             launch_transpose<T, false>(nr, lb, C + r0 * lb, Ct, st);
-            launch_row_sweep<T>(B, nr, Ct, St, false, st);
+            launch_row_sweep<T>(B, nr, Ct, St, false, st, c.det);
             launch_transpose<T, true>(lb, nr, St, S + r0 * lb, st);
         }
     }
     timing_mark(c, 2, prec, st);
+    if ((terms & 4) && c.det) det_scale(c, C, la * lb, st);
     if (!(terms & 4)) {
     } else if (!launch_ab<T>(c, C, S, st)) {
         const int64_t ncb = (lb + kBlock - 1) / kBlock;
@@ -1092,6 +1171,7 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
         Ctx &c = *ctx[i];
         const Spin &A = c.sp[0], &B = c.sp[1];
         T *Ct = (T *)ctx_workspace(c), *St = Ct + (size_t)A.l * B.l;
+        if (c.det) det_scale(c, C[i], A.l * B.l, st);
         sweep(sa, bsa, A, B.l, C[i], S[i]);
         trans(t1, bt1, A.l, B.l, C[i], Ct);
         sweep(sb, bsb, B, A.l, Ct, St);
@@ -1108,7 +1188,8 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
                 g = &sgroups.back();
             }
             g->d.push_back(SlabDesc{g->blocks, B.l, L, A.s_ptr, A.s_ent, B.s_ptr, B.g_ent,
-                                    B.g_off, Vals<T>::V(c), C[i], S[i]});
+                                    B.g_off, Vals<T>::V(c), C[i], S[i],
+                                    c.det ? c.det_buf + 1 : nullptr});
             g->blocks += A.l;
             g->lds = std::max(g->lds, L.total);
             continue;

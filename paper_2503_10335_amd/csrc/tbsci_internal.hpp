@@ -139,6 +139,12 @@ struct Ctx {
     Dets *dets = nullptr;       // TBSCI space, or nullptr for the whole TPB space
     std::vector<int32_t> irreps; // orbital irreps once a symmetry is set (else empty)
     int target_irrep = -1;
+    // deterministic sigma (tbsci_set_deterministic): the opposite-spin row
+    // accumulates in fixed point, the sweeps run in one fixed order;
+    // det_buf[0] = max |C| bits, det_buf[1] = the fixed-point scale
+    bool det = false;
+    double maxV = 0.0;           // largest |(pq|rs)|
+    double *det_buf = nullptr;
     // alpha and beta lists are the same strings in the same order with
     // N_alpha = N_beta: H commutes with the spin flip C -> C^T (up to the
     // sign (-1)^N), and the solvers work in the C^T = C and C^T = -C

@@ -111,6 +111,7 @@ def load():
         "tbsci_list_size": (c_int, [P, c_int, c_int, P]),
         "tbsci_get_list": (c_int, [P, c_int, c_int, P, P, P]),
         "tbsci_timing_enable": (c_int, [P, c_int]),
+        "tbsci_set_deterministic": (c_int, [P, c_int]),
         "tbsci_timing_read": (c_int, [P, c_int, c_int, P, P, P, P, P]),
         "tbsci_timing_executed_flops": (c_int, [P, c_int, c_int, P]),
         "tbsci_sigma_batch": (c_int, [P, c_int, P, P, c_int, P]),
@@ -273,6 +274,10 @@ def tbsci_get_list(ctx, spin, kind, l):
 
 
 TBSCI_N_KERNELS = 3
+
+
+def tbsci_set_deterministic(ctx, enable=True):
+    _check(load().tbsci_set_deterministic(ctx, 1 if enable else 0))
 
 
 def tbsci_timing_enable(ctx, enable=True):
@@ -502,6 +507,10 @@ class Context:
 
     def _shape(self):
         return (self.n_det,) if getattr(self, "compact", False) else (self.l_alpha, self.l_beta)
+
+    def set_deterministic(self, enable=True):
+        """Bitwise-reproducible sigma for this context (alone or batched)."""
+        tbsci_set_deterministic(self._ctx, enable)
 
     def mfma_flops(self, precision=TBSCI_FP64):
         """Flops one launch of the opposite-spin kernel executes (padded tiles)."""

@@ -1,0 +1,192 @@
+"""GPU tests of the reproducible sigma mode (tbsci_set_deterministic)
+through the C ABI.
+
+In this mode the opposite-spin term sums every output element in 64-bit
+fixed point and the same-spin sweeps run in one fixed order, so sigma must
+be bitwise equal across runs, and a problem's sigma built alone must be
+bitwise equal to its sigma built inside a batch (the grouped launches).
+Parity with the oracle keeps the FP64 bar (1e-12 relative) and the FP32 bar
+(2e-5 relative): the fixed-point rounding is 2^-62 of a bound on the
+element's partial sums, far below both.
+"""
+import numpy as np
+import pytest
+
+from paper_2503_10335_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_2503_10335_amd import tbsci as T
+    T.load()
+    return T, O, torch
+
+
+def _shell_alpha(M, N):
+    """The lowest string (orbitals 0..N-1) and all of its single excitations."""
+    ref = (1 << N) - 1
+    out = [ref] + [ref ^ (1 << i) ^ (1 << a) for i in range(N) for a in range(N, M)]
+    return np.array(out, dtype=np.uint64)
+
+
+def _shell_m20():
+    """110 links on the reference alpha string: the global-fragment kernel."""
+    M, N = 20, 10
+    h, eri = W.integrals(M, 41)
+    rng = np.random.default_rng(42)
+    B = W.all_strings(M, N)
+    beta = np.ascontiguousarray(B[rng.permutation(len(B))[:60]])
+    return W.Problem("shell_m20", M, N, N, h, eri, _shell_alpha(M, N), beta)
+
+
+# slab kernel (three shapes, one with spin-flip lists), global-fragment
+# kernel with many links, global-fragment kernel with a long whole FP64 row,
+# chunked same-spin sweeps in the default mode (3200 alpha strings)
+PROBS = {
+    "fci_m8": lambda: W.config("fci_m8"),
+    "rand_m12_4_6": lambda: W.random_selection(12, 4, 6, 300, 257, seed=13),
+    "ranked_m12": lambda: W.make_problem("ranked_m12", 12, 6, 500, 14, 24),
+    "shell_m20": _shell_m20,
+    "long_24_18000": lambda: W.random_selection(18, 9, 9, 24, 18000, seed=43),
+    "chunked_3200_40": lambda: W.random_selection(14, 7, 7, 3200, 40, seed=31),
+}
+# Davidson problems that converge to a 1e-8 residual within 200 iterations
+DAV = {
+    "fci_m8": PROBS["fci_m8"],
+    "rand_m10_5_5": lambda: W.random_selection(10, 5, 5, 130, 97, seed=12),
+    "ranked_m11_indep": lambda: W.make_problem("ranked_m11", 11, 5, 200, 15, 25,
+                                               independent_beta=True),
+    "rand_m12_4_6": PROBS["rand_m12_4_6"],
+}
+_cache = {}
+
+
+def _problem(name):
+    if name not in _cache:
+        _cache[name] = {**PROBS, **DAV}[name]()
+    return _cache[name]
+
+
+def _rel(a, b):
+    n = np.linalg.norm(b)
+    return (np.linalg.norm(a - b) / n if n > 0 else np.linalg.norm(a),
+            np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _vector(ctx, seed):
+    return np.random.default_rng(seed).normal(size=(ctx.l_alpha, ctx.l_beta))
+
+
+@pytest.mark.parametrize("name", list(PROBS))
+def test_deterministic_sigma_parity_and_repeat(env, name):
+    """Oracle parity (all rows, or eight sampled rows of a long space) and
+    three runs bitwise equal, FP64 and FP32."""
+    T, O, torch = env
+    p = _problem(name)
+    print(f"deterministic sigma: {name} {len(p.alpha)} x {len(p.beta)}", flush=True)
+    ctx = T.Context.from_problem(p)
+    ctx.set_deterministic(True)
+    C = _vector(ctx, 5)
+    la = ctx.l_alpha
+    rows = None
+    if la * ctx.l_beta > 200000:
+        rows = np.unique(np.r_[0, la - 1, np.random.default_rng(7).choice(la, 6, replace=False)])
+    sp = O.Space.of(p)
+    ref = sp.sigma(C, rows=rows, nthreads=16) if rows is not None else sp.sigma(C, nthreads=16)
+    Cg = torch.from_numpy(C).cuda()
+    det64 = None
+    for prec, tol in ((T.TBSCI_FP64, 1e-12), (T.TBSCI_FP32, 2e-5)):
+        X = Cg if prec == T.TBSCI_FP64 else Cg.float()
+        runs = [ctx.sigma(X, precision=prec).cpu().numpy() for _ in range(3)]
+        for r in runs[1:]:
+            assert np.array_equal(r.view(np.uint8), runs[0].view(np.uint8)), prec
+        got = runs[0].astype(np.float64)
+        if prec == T.TBSCI_FP64:
+            det64 = got
+        e, m = _rel(got if rows is None else got[rows], ref)
+        assert e <= tol and (prec != T.TBSCI_FP64 or m <= tol), (prec, e, m)
+    # the default mode agrees with the reproducible one to the parity bar
+    ctx.set_deterministic(False)
+    e, m = _rel(ctx.sigma(Cg).cpu().numpy(), det64)
+    assert e <= 1e-12 and m <= 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deterministic_sigma_alone_equals_batch(env, prec):
+    """Each problem's sigma built alone (tbsci_sigma) equals, bit for bit,
+    its sigma built in one tbsci_sigma_batch call with the other problems
+    (shared sweep, transpose and slab launches; the global-fragment problems
+    run their own opposite-spin launch)."""
+    T, O, torch = env
+    names = ["fci_m8", "rand_m12_4_6", "ranked_m12", "shell_m20", "chunked_3200_40"]
+    ctxs = [T.Context.from_problem(_problem(n)) for n in names]
+    P = T.TBSCI_FP64 if prec == "fp64" else T.TBSCI_FP32
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Cs = [torch.from_numpy(_vector(c, 11 + i)).to(dt).cuda() for i, c in enumerate(ctxs)]
+    for c in ctxs:
+        c.set_deterministic(True)
+    alone = [c.sigma(C, precision=P).cpu().numpy() for c, C in zip(ctxs, Cs)]
+    for _ in range(2):
+        batch = [S.cpu().numpy() for S in T.sigma_batch(ctxs, Cs, precision=P)]
+        for n, a, b in zip(names, alone, batch):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), n
+    # the no-allocation entry point gives the same bits
+    for c, C, a in zip(ctxs, Cs, alone):
+        S = torch.empty_like(C)
+        T.tbsci_sigma_noalloc(c.handle, C, S, P)
+        assert np.array_equal(S.cpu().numpy().view(np.uint8), a.view(np.uint8))
+    for c in ctxs:
+        c.close()
+
+
+def test_deterministic_rejects_split_rows(env):
+    """Opposite-spin rows longer than LDS (l_beta = 21000) are built with
+    global atomics, so the reproducible mode refuses them with an error,
+    and the default mode still builds them."""
+    T, O, torch = env
+    p = W.random_selection(18, 9, 9, 16, 21000, seed=43)
+    ctx = T.Context.from_problem(p)
+    C = torch.from_numpy(_vector(ctx, 6)).cuda()
+    ctx.set_deterministic(True)
+    with pytest.raises(T.TbsciError, match="deterministic"):
+        ctx.sigma(C)
+        torch.cuda.synchronize()
+    ctx.set_deterministic(False)
+    S = ctx.sigma(C)
+    torch.cuda.synchronize()
+    assert torch.isfinite(S).all()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_deterministic_davidson_alone_equals_batch(env, prec):
+    """With reproducible sigma, a Davidson solve alone (tbsci_davidson) and
+    the same solve in a lock-step batch with other problems
+    (tbsci_davidson_batch) give bitwise equal energies and iteration
+    counts: the solver's own reductions are fixed-order per problem.  The
+    energies agree with the default mode's to 1e-8 Eh (FP64; 1e-6 Eh for
+    the mixed solves, converged to a 1e-5 residual)."""
+    T, O, torch = env
+    names = list(DAV)
+    ctxs = [T.Context.from_problem(_problem(n)) for n in names]
+    P = T.TBSCI_FP64 if prec == "fp64" else T.TBSCI_MIXED
+    tol = 1e-8 if prec == "fp64" else 1e-5
+    ref = [c.davidson(precision=P, tol_resid=tol)[0] for c in ctxs]
+    for c in ctxs:
+        c.set_deterministic(True)
+    alone = [c.davidson(precision=P, tol_resid=tol)[0] for c in ctxs]
+    batch = T.davidson_batch(ctxs, precision=P, tol_resid=tol)
+    for n, r, a, b in zip(names, ref, alone, batch):
+        assert a["converged"] == 1 and b["converged"] == 1, (n, a, b)
+        assert a["energy"] == b["energy"], (n, a["energy"], b["energy"])
+        assert a["iters"] == b["iters"], n
+        assert abs(a["energy"] - r["energy"]) < (1e-8 if prec == "fp64" else 1e-6), n
+    for c in ctxs:
+        c.close()

@@ -237,11 +237,14 @@ int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int pr
  * partial sum can overflow -- so the order of its atomic adds no longer
  * matters; the same-spin sweeps run in one fixed order.  Rounding: each
  * opposite-spin contribution is rounded to 2^-62 of that bound, below the
- * FP64 parity tolerance for any C.  Opposite-spin rows must fit in LDS
- * (l_beta up to about 20,000 strings, the global-fragment kernel's FP64
- * row); longer rows fail with TBSCI_E_INVAL while the mode is on.
- * Allocates 16 bytes on the first enable.  enable == 0 returns to the
- * default (FP64 atomics, chunked and panel sweeps).
+ * FP64 parity tolerance for any C.  Opposite-spin rows longer than LDS
+ * holds (l_beta above about 20,000 strings) keep their remainder in a
+ * device staging area of l_alpha x (l_beta - that length) 8-byte entries,
+ * allocated here on enable (11 GB at l_alpha = l_beta = 48,620) and left
+ * zeroed by every sigma; FP32 sigma then also keeps an 8-byte row.  The
+ * call allocates 16 bytes plus that area (TBSCI_E_DEVICE when it does not
+ * fit); the memory is held until tbsci_destroy.  enable == 0 returns to
+ * the default (FP64 atomics, chunked and panel sweeps).
  */
 int tbsci_set_deterministic(tbsci_ctx *ctx, int enable);
 

@@ -86,7 +86,7 @@ void destroy_ctx(Ctx *c) {
     timing_clear(*c);
     free_dets(*c);
     for (auto &s : c->sp) free_spin(s);
-    void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work, c->det_buf};
+    void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work, c->det_buf, c->det_stage};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -460,9 +460,18 @@ int tbsci_set_deterministic(tbsci_ctx *ctx, int enable) {
     return guarded([&]() -> int {
         check_ctx(ctx);
         Ctx *c = ctx_of(ctx);
-        if (enable && !c->det_buf) {
+        if (enable) {
             TB_HIP(hipSetDevice(c->device));
-            c->det_buf = dalloc<double>(2);
+            if (!c->det_buf) c->det_buf = dalloc<double>(2);
+            const int64_t n = det_stage_entries(*c);
+            if (n > c->det_stage_n) {
+                if (c->det_stage) TB_HIP(hipFree(c->det_stage));
+                c->det_stage = nullptr;
+                c->det_stage_n = 0;
+                c->det_stage = dalloc<unsigned long long>((size_t)n);
+                TB_HIP(hipMemset(c->det_stage, 0, (size_t)n * 8));
+                c->det_stage_n = n;
+            }
         }
         c->det = enable != 0;
         return TBSCI_OK;

@@ -647,17 +647,20 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
                                              const Ent *__restrict__ sb_grp,
                                              const int32_t *__restrict__ sb_off,
                                              const T *__restrict__ V, const T *__restrict__ C,
-                                             T *__restrict__ S, const double *__restrict__ det) {
+                                             T *__restrict__ S, const double *__restrict__ det,
+                                             unsigned long long *__restrict__ stage) {
     using M = Mfma<T>;
     using R = typename std::conditional<ROW == kRowT || ROW == kRowSplitT, T, double>::type;
     constexpr bool kSplit = ROW == kRowSplit || ROW == kRowSplitT;
     const int64_t nrow = kSplit ? L.nrow : lb;
     extern __shared__ __align__(16) unsigned char smem[];
     R *row = (R *)(smem + L.row);
-    // fixed-point row (det) only with a whole FP64 row in LDS
+    // fixed-point row (det): the 8-byte row in LDS, and for a split row the
+    // rest in this row's segment of the fixed-point staging area
     unsigned long long *rowi = (unsigned long long *)(smem + L.row);
-    const bool fixed = ROW == kRowF64 && det;
+    const bool fixed = (ROW == kRowF64 || ROW == kRowSplit) && det;
     const double dscale = fixed ? *det : 0.0;
+    unsigned long long *srow = fixed && kSplit ? stage + I * (lb - nrow) : nullptr;
     int32_t *aj = (int32_t *)(smem + L.aj);
     int32_t *apq = (int32_t *)(smem + L.apq);
     int *ctr = (int *)(smem + L.ctr);
@@ -772,7 +775,8 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
                 T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
                 if ((e.o >> 12) & 1u) v = -v;
                 if (fixed)
-                    atomicAdd(&rowi[e.j], to_fixed((double)v, dscale));
+                    atomicAdd(!kSplit || e.j < nrow ? &rowi[e.j] : &srow[e.j - nrow],
+                              to_fixed((double)v, dscale));
                 else if (!kSplit || e.j < nrow)
                     atomicAdd(&row[e.j], (R)v);
                 else
@@ -785,11 +789,20 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
             for (int32_t x = o0 + 4; x < o1; ++x) put(sb_grp[base + x]);
         }
     }
+    // the staged part of a split row: every add to it came from this block;
+    // the fence makes them complete at device scope before they are read
+    // back (and the segment cleared for the next call) with exchanges
+    if (fixed && kSplit) __threadfence();
     __syncthreads();
-    if (fixed)
+    if (fixed) {
         for (int64_t i = tid; i < nrow; i += nthr)
             S[I * lb + i] = (T)((double)S[I * lb + i] + from_fixed(rowi[i], dscale));
-    else
+        if (kSplit)
+            for (int64_t i = nrow + tid; i < lb; i += nthr)
+                S[I * lb + i] =
+                    (T)((double)S[I * lb + i] +
+                        from_fixed(atomicExch(&srow[i - nrow], 0ull), dscale));
+    } else
         for (int64_t i = tid; i < nrow; i += nthr)
             S[I * lb + i] = (T)((R)S[I * lb + i] + row[i]);
 }
@@ -804,9 +817,10 @@ __global__ __launch_bounds__(kSlabBlock) void k_ab_slabg(int64_t lb, int P, int 
                                                         const T *__restrict__ V,
                                                         const T *__restrict__ C,
                                                         T *__restrict__ S,
-                                                        const double *__restrict__ det) {
+                                                        const double *__restrict__ det,
+                                                        unsigned long long *__restrict__ stage) {
     ab_slabg_row<T, KS, ROW>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off,
-                             V, C, S, det);
+                             V, C, S, det, stage);
 }
 
 // one problem of a grouped slab launch: blocks [blk0, blk0 + l_alpha)
@@ -941,7 +955,8 @@ void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
     SlabgLds L = slabg_lds(B.l, ks, 8);
     if (L.nrow < B.l) {
         row = kRowSplit;
-        if (sizeof(T) < 8) {
+        // deterministic mode keeps the 8-byte fixed-point row in every precision
+        if (sizeof(T) < 8 && !c.det) {
             // an FP32 sigma keeps a whole FP32 row when that fits, else the
             // longer FP32 part of a split row
             const SlabgLds Lt = slabg_lds(B.l, ks, sizeof(T), B.l);
@@ -954,9 +969,9 @@ void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
             }
         }
     }
-    if (c.det && row != kRowF64)
-        throw Error(TBSCI_E_INVAL, "deterministic sigma needs each FP64 output row in LDS "
-                                   "(l_beta too long)");
+    if (c.det && row == kRowSplit &&
+        (!c.det_stage || c.det_stage_n < A.l * (B.l - L.nrow)))
+        throw Error(TBSCI_E_STATE, "deterministic sigma: the fixed-point staging area is missing");
     auto f = row == kRowF64      ? k_ab_slabg<T, KS, kRowF64>
              : row == kRowT      ? k_ab_slabg<T, KS, kRowT>
              : row == kRowSplitT ? k_ab_slabg<T, KS, kRowSplitT>
@@ -964,7 +979,8 @@ void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
     if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
     f<<<(unsigned)A.l, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
                                                   B.g_ent, B.g_off, Vals<T>::V(c), C, S,
-                                                  c.det ? c.det_buf + 1 : nullptr);
+                                                  c.det ? c.det_buf + 1 : nullptr,
+                                                  c.det ? c.det_stage : nullptr);
     TB_HIP(hipGetLastError());
 }
 
@@ -1092,9 +1108,14 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work,
         if (marks) ::tbsci::timing_mark(cc, index, pr, s2);
     };
 
+    // deterministic mode: a problem that can share grouped launches (its
+    // beta sweep in one block) sweeps in the grouped sweep's one fixed
+    // order; the others are never grouped and keep the panel and chunked
+    // sweeps, whose order is fixed too
+    const bool fixed = c.det && beta_block_rows(la, lb, kWorkCap) >= la;
     timing_mark(c, 0, prec, st);
     if (terms & 1)
-        launch_row_sweep<T>(A, lb, C, S, false, st, c.det);  // sigma = A_a C
+        launch_row_sweep<T>(A, lb, C, S, false, st, fixed);  // sigma = A_a C
     else
         launch_zero<T>(la * lb, S, st);
     timing_mark(c, 1, prec, st);
@@ -1104,7 +1125,7 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work,
         for (int64_t r0 = 0; r0 < la; r0 += rb) {
             const int64_t nr = std::min(rb, la - r0);
             launch_transpose<T, false>(nr, lb, C + r0 * lb, Ct, st);
-            launch_row_sweep<T>(B, nr, Ct, St, false, st, c.det);
+            launch_row_sweep<T>(B, nr, Ct, St, false, st, fixed);
             launch_transpose<T, true>(lb, nr, St, S + r0 * lb, st);
         }
     }
@@ -1225,6 +1246,17 @@ void sigma_group_impl(Ctx *const *ctx, const T *const *C, T *const *S, int n, Ta
 }
 
 }  // namespace
+
+// entries of the fixed-point staging area that deterministic sigma needs:
+// the part of each alpha row beyond the LDS row of the global-fragment
+// kernel (0 when whole rows fit, or another kernel takes the shape)
+int64_t det_stage_entries(const Ctx &c) {
+    if (!slabg_fits(c)) return 0;
+    const Spin &A = c.sp[0], &B = c.sp[1];
+    const int ks = std::max((A.max_s + 3) / 4, 1);
+    const SlabgLds L = slabg_lds(B.l, ks, 8);
+    return L.nrow < B.l ? A.l * (B.l - L.nrow) : 0;
+}
 
 void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, int n,
                         int precision, TableArena &ar, hipStream_t st) {

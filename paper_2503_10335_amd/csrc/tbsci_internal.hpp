@@ -145,6 +145,10 @@ struct Ctx {
     bool det = false;
     double maxV = 0.0;           // largest |(pq|rs)|
     double *det_buf = nullptr;
+    // rows longer than LDS: the rest of each row in fixed point, left zeroed
+    // by every sigma (det_stage_n entries)
+    unsigned long long *det_stage = nullptr;
+    int64_t det_stage_n = 0;
     // alpha and beta lists are the same strings in the same order with
     // N_alpha = N_beta: H commutes with the spin flip C -> C^T (up to the
     // sign (-1)^N), and the solvers work in the C^T = C and C^T = -C
@@ -290,6 +294,8 @@ void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st,
 // sweep runs in blocks that fit; throws TBSCI_E_INVAL when one row does
 // not); marks: record the measurement events when timing is on (they are
 // created on first use, an allocation)
+// fixed-point staging entries deterministic sigma needs for this context
+int64_t det_stage_entries(const Ctx &c);
 void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
                      void *work, size_t work_bytes, bool marks);
 double executed_flops(Ctx &c, int kernel, int precision);

@@ -47,7 +47,8 @@ def _shell_m20():
 
 # slab kernel (three shapes, one with spin-flip lists), global-fragment
 # kernel with many links, global-fragment kernel with a long whole FP64 row,
-# chunked same-spin sweeps in the default mode (3200 alpha strings)
+# chunked same-spin sweeps in the default mode (3200 alpha strings), rows
+# longer than LDS (part of each row in the fixed-point staging area)
 PROBS = {
     "fci_m8": lambda: W.config("fci_m8"),
     "rand_m12_4_6": lambda: W.random_selection(12, 4, 6, 300, 257, seed=13),
@@ -55,6 +56,8 @@ PROBS = {
     "shell_m20": _shell_m20,
     "long_24_18000": lambda: W.random_selection(18, 9, 9, 24, 18000, seed=43),
     "chunked_3200_40": lambda: W.random_selection(14, 7, 7, 3200, 40, seed=31),
+    "split_16_21000": lambda: W.random_selection(18, 9, 9, 16, 21000, seed=43),
+    "split_10_45000": lambda: W.random_selection(18, 9, 9, 10, 45000, seed=43),
 }
 # Davidson problems that converge to a 1e-8 residual within 200 iterations
 DAV = {
@@ -125,7 +128,8 @@ def test_deterministic_sigma_alone_equals_batch(env, prec):
     (shared sweep, transpose and slab launches; the global-fragment problems
     run their own opposite-spin launch)."""
     T, O, torch = env
-    names = ["fci_m8", "rand_m12_4_6", "ranked_m12", "shell_m20", "chunked_3200_40"]
+    names = ["fci_m8", "rand_m12_4_6", "ranked_m12", "shell_m20", "chunked_3200_40",
+             "split_16_21000"]
     ctxs = [T.Context.from_problem(_problem(n)) for n in names]
     P = T.TBSCI_FP64 if prec == "fp64" else T.TBSCI_FP32
     dt = torch.float64 if prec == "fp64" else torch.float32
@@ -146,22 +150,29 @@ def test_deterministic_sigma_alone_equals_batch(env, prec):
         c.close()
 
 
-def test_deterministic_rejects_split_rows(env):
-    """Opposite-spin rows longer than LDS (l_beta = 21000) are built with
-    global atomics, so the reproducible mode refuses them with an error,
-    and the default mode still builds them."""
+def test_deterministic_staging_left_clear(env):
+    """Rows longer than LDS stage their remainder in fixed point; every
+    sigma leaves that area zeroed, so sigma of a second vector, then of the
+    first again, match their own first results bit for bit (a leftover
+    would add the previous vector's opposite-spin term), and switching the
+    mode off and on keeps it."""
     T, O, torch = env
-    p = W.random_selection(18, 9, 9, 16, 21000, seed=43)
+    p = _problem("split_16_21000")
     ctx = T.Context.from_problem(p)
-    C = torch.from_numpy(_vector(ctx, 6)).cuda()
     ctx.set_deterministic(True)
-    with pytest.raises(T.TbsciError, match="deterministic"):
-        ctx.sigma(C)
-        torch.cuda.synchronize()
+    C1 = torch.from_numpy(_vector(ctx, 6)).cuda()
+    C2 = torch.from_numpy(_vector(ctx, 9)).cuda()
+    a1 = ctx.sigma(C1).cpu().numpy()
+    a2 = ctx.sigma(C2).cpu().numpy()
     ctx.set_deterministic(False)
-    S = ctx.sigma(C)
-    torch.cuda.synchronize()
-    assert torch.isfinite(S).all()
+    d2 = ctx.sigma(C2).cpu().numpy()
+    ctx.set_deterministic(True)
+    b1 = ctx.sigma(C1).cpu().numpy()
+    b2 = ctx.sigma(C2).cpu().numpy()
+    assert np.array_equal(a1.view(np.uint8), b1.view(np.uint8))
+    assert np.array_equal(a2.view(np.uint8), b2.view(np.uint8))
+    e, m = _rel(a2, d2)
+    assert e <= 1e-12 and m <= 1e-12
     ctx.close()
 
 

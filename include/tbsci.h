@@ -249,6 +249,46 @@ int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int pr
 int tbsci_set_deterministic(tbsci_ctx *ctx, int enable);
 
 /*
+ * Method of the two same-spin terms (A_alpha C and C A_beta^T; the [2,0],
+ * [0,2] categories and the same-spin parts of [1,0], [0,1], [0,0] of
+ * Sec. II.C):
+ *   TBSCI_SAME_SPIN_CSR   sparse sweeps over the stored same-spin operator
+ *                         (each output row gathers the rows of C its
+ *                         singles and doubles reach)
+ *   TBSCI_SAME_SPIN_HOLE  hole-pair form: for every (N-2)-electron string
+ *                         K contained in the spin's strings, the rows of C
+ *                         of the strings K + {q, s} times the dense block
+ *                         of the pair operator
+ *                         W[pr][qs] = (pq|rs) - (ps|rq)
+ *                                   + (h_pq d_rs + h_rs d_pq - h_ps d_rq - h_rq d_ps) / (N - 1)
+ *                         on MFMA, each string K + {p, r} reading its row
+ *                         of the product back (the one-body part folded
+ *                         into W; both ends run over the spin's strings
+ *                         only, so the projection is exact)
+ *   TBSCI_SAME_SPIN_AUTO  (the default) the hole-pair form for a spin
+ *                         whose hole strings hold at least
+ *                         TBSCI_HOLE_AUTO_MIN strings on average, in a
+ *                         space too large for grouped launches (the beta
+ *                         sweep in blocks, above 2^27 determinants) with
+ *                         no point-group symmetry set; else CSR
+ * A spin with fewer than 2 electrons, or with a hole string contained in
+ * more than 128 of its strings, keeps the CSR sweep.  The hole-pair index
+ * (built by tbsci_create for the spins the automatic method takes, else
+ * here) copies the strings and integrals to the host, sorts N(N-1)/2
+ * entries per string and holds about 16 B per entry on the device; the
+ * hole-pair sweep also allocates a product buffer of up to 2 GiB on first
+ * use.  A context on the hole-pair sweep builds its sigma alone in batched
+ * calls.  tbsci_sigma_noalloc always uses CSR.  tbsci_timing_executed_flops
+ * of kernels 0 and 1 reports the MFMA work of the hole-pair sweep when it
+ * is on.
+ */
+#define TBSCI_SAME_SPIN_AUTO 0
+#define TBSCI_SAME_SPIN_CSR 1
+#define TBSCI_SAME_SPIN_HOLE 2
+#define TBSCI_HOLE_AUTO_MIN 32
+int tbsci_set_same_spin(tbsci_ctx *ctx, int method);
+
+/*
  * Diagonal H_KK of every determinant (Sec. II.C: the [0,0] category,
  * precomputed and stored), device double [l_alpha][l_beta], asynchronous.
  */

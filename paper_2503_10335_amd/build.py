@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtbsci.so")
 SOURCES = ["api.hip", "index_kernels.hip", "sigma_kernels.hip", "davidson.hip", "batch.hip", "server.hip",
-           "noalloc.hip", "dets.hip", "sym.hip", "select.hip"]
+           "noalloc.hip", "dets.hip", "sym.hip", "select.hip", "hole_sweep.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

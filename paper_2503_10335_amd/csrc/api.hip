@@ -70,6 +70,7 @@ T *dalloc(size_t n) {
 }
 
 void free_spin(Spin &s) {
+    free_hole(s);
     void *ptrs[] = {s.str,   s.keys,  s.pos,     s.s_ptr, s.s_ent, s.d_ptr, s.d_ent,
                     s.a_ptr, s.a_col, s.a_val,   s.a_val32, s.dsame, s.jocc,  s.g_ent,
                     s.g_off, s.b_off, s.b_col,   s.b_val, s.b_val32};
@@ -86,7 +87,8 @@ void destroy_ctx(Ctx *c) {
     timing_clear(*c);
     free_dets(*c);
     for (auto &s : c->sp) free_spin(s);
-    void *ptrs[] = {c->h, c->eri, c->V64, c->V32, c->work, c->det_buf, c->det_stage};
+    void *ptrs[] = {c->h,       c->eri,     c->V64,     c->V32,
+                    c->work,    c->det_buf, c->det_stage, c->hole_work};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -265,6 +267,9 @@ Ctx *create_ctx(int M, int n_alpha, int n_beta, const double *h, const double *e
                 build_spin(*c, c->sp[0], alpha, st);
                 build_spin(*c, c->sp[1], beta, st);
                 TB_HIP(hipStreamSynchronize(st));
+                // hole-pair index of the spins the automatic method gives it to
+                hole_build(*c, 0, false);
+                hole_build(*c, 1, false);
             } catch (...) {
                 (void)hipStreamSynchronize(st);
                 (void)hipStreamDestroy(st);
@@ -474,6 +479,23 @@ int tbsci_set_deterministic(tbsci_ctx *ctx, int enable) {
             }
         }
         c->det = enable != 0;
+        return TBSCI_OK;
+    });
+}
+
+int tbsci_set_same_spin(tbsci_ctx *ctx, int method) {
+    return guarded([&]() -> int {
+        check_ctx(ctx);
+        Ctx *c = ctx_of(ctx);
+        if (method != TBSCI_SAME_SPIN_AUTO && method != TBSCI_SAME_SPIN_CSR &&
+            method != TBSCI_SAME_SPIN_HOLE)
+            throw Error(TBSCI_E_INVAL, "unknown same-spin method");
+        if (method != TBSCI_SAME_SPIN_CSR) {
+            TB_HIP(hipSetDevice(c->device));
+            hole_build(*c, 0, method == TBSCI_SAME_SPIN_HOLE);
+            hole_build(*c, 1, method == TBSCI_SAME_SPIN_HOLE);
+        }
+        c->same_spin = method;
         return TBSCI_OK;
     });
 }

@@ -849,6 +849,12 @@ __global__ __launch_bounds__(kSlabBlock) void g_ab_slab(const SlabDesc *__restri
 
 // the context's beta-sweep workspace (sigma_work_bytes), allocated on
 // first use
+// whether a problem may share the grouped launches of a batch: its beta
+// sweep in one block, and the CSR sweeps for both spins
+bool groupable(const Ctx &c) {
+    return !hole_any(c) && beta_block_rows(c.sp[0].l, c.sp[1].l, kWorkCap) >= c.sp[0].l;
+}
+
 void *ctx_workspace(Ctx &c) {
     const size_t need = sigma_work_bytes(c.sp[0].l, c.sp[1].l);
     if (c.work_bytes < need) {
@@ -1100,7 +1106,7 @@ void det_scale(Ctx &c, const T *C, int64_t n, hipStream_t st) {
 // 2 l_beta rb elements of type T (C^T and the sweep result of a block)
 template <typename T>
 void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work, int64_t rb,
-                bool marks) {
+                bool marks, void *hwork, size_t hbytes) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     const int64_t la = A.l, lb = B.l;
     const int prec = sizeof(T) == 8 ? TBSCI_FP64 : TBSCI_FP32;
@@ -1112,10 +1118,15 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work,
     // beta sweep in one block) sweeps in the grouped sweep's one fixed
     // order; the others are never grouped and keep the panel and chunked
     // sweeps, whose order is fixed too
-    const bool fixed = c.det && beta_block_rows(la, lb, kWorkCap) >= la;
+    const bool fixed = c.det && groupable(c);
+    // hole-pair sweeps (with their product buffer; never in the
+    // no-allocation entry point)
+    const bool ha = hwork && hole_on(c, 0), hb = hwork && hole_on(c, 1);
     timing_mark(c, 0, prec, st);
-    if (terms & 1)
-        launch_row_sweep<T>(A, lb, C, S, false, st, fixed);  // sigma = A_a C
+    if ((terms & 1) && ha)
+        hole_sweep(c, 0, lb, C, S, prec, hwork, hbytes, st);  // sigma = A_a C
+    else if (terms & 1)
+        launch_row_sweep<T>(A, lb, C, S, false, st, fixed);
     else
         launch_zero<T>(la * lb, S, st);
     timing_mark(c, 1, prec, st);
@@ -1125,7 +1136,10 @@ void sigma_impl(Ctx &c, const T *C, T *S, hipStream_t st, int terms, void *work,
         for (int64_t r0 = 0; r0 < la; r0 += rb) {
             const int64_t nr = std::min(rb, la - r0);
             launch_transpose<T, false>(nr, lb, C + r0 * lb, Ct, st);
-            launch_row_sweep<T>(B, nr, Ct, St, false, st, fixed);
+            if (hb)
+                hole_sweep(c, 1, nr, Ct, St, prec, hwork, hbytes, st);
+            else
+                launch_row_sweep<T>(B, nr, Ct, St, false, st, fixed);
             launch_transpose<T, true>(lb, nr, St, S + r0 * lb, st);
         }
     }
@@ -1269,8 +1283,7 @@ void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, i
     std::vector<void *> gS;
     std::vector<int> later;
     for (int i = 0; i < n; ++i) {
-        const int64_t la = ctx[i]->sp[0].l, lb = ctx[i]->sp[1].l;
-        if (n == 1 || beta_block_rows(la, lb, kWorkCap) < la) {
+        if (n == 1 || !groupable(*ctx[i])) {
             launch_sigma(*ctx[i], C[i], S[i], precision, st);
         } else if (std::find(gc.begin(), gc.end(), ctx[i]) != gc.end()) {
             later.push_back(i);
@@ -1294,7 +1307,10 @@ void launch_sigma_group(Ctx *const *ctx, const void *const *C, void *const *S, i
     for (int i : later) launch_sigma(*ctx[i], C[i], S[i], precision, st);
 }
 
-void reserve_sigma_workspace(Ctx &c) { (void)ctx_workspace(c); }
+void reserve_sigma_workspace(Ctx &c) {
+    (void)ctx_workspace(c);
+    if (hole_any(c)) (void)hole_workspace(c);
+}
 
 void timing_mark(Ctx &c, int index, int precision, hipStream_t st) {
     if (!c.timing) return;
@@ -1315,7 +1331,7 @@ void timing_clear(Ctx &c) {
 }
 
 void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
-                     void *work, size_t work_bytes, bool marks) {
+                     void *work, size_t work_bytes, bool marks, void *hwork, size_t hbytes) {
     const int64_t la = c.sp[0].l, lb = c.sp[1].l;
     int64_t rb = la;
     if (terms & 2) {
@@ -1324,14 +1340,18 @@ void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t 
             throw Error(TBSCI_E_INVAL, "the workspace cannot hold the beta sweep of one alpha row");
     }
     if (precision == TBSCI_FP64)
-        sigma_impl<double>(c, (const double *)C, (double *)S, st, terms, work, rb, marks);
+        sigma_impl<double>(c, (const double *)C, (double *)S, st, terms, work, rb, marks, hwork,
+                           hbytes);
     else
-        sigma_impl<float>(c, (const float *)C, (float *)S, st, terms, work, rb, marks);
+        sigma_impl<float>(c, (const float *)C, (float *)S, st, terms, work, rb, marks, hwork,
+                          hbytes);
 }
 
 void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms) {
     void *w = ctx_workspace(c);
-    launch_sigma_ws(c, C, S, precision, st, terms, w, c.work_bytes, true);
+    void *hw = hole_any(c) ? hole_workspace(c) : nullptr;
+    launch_sigma_ws(c, C, S, precision, st, terms, w, c.work_bytes, true, hw,
+                    hw ? c.hole_work_bytes : 0);
 }
 
 // Floating-point operations one launch of kernel `kernel` executes: for the
@@ -1341,6 +1361,10 @@ void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st,
 // direct fallback the multiply-adds of their sums.
 double executed_flops(Ctx &c, int kernel, int precision) {
     const Spin &A = c.sp[0], &B = c.sp[1];
+    // hole-pair sweeps: each hole string's padded product block times the
+    // columns, rounded up to the 16-column MFMA tile
+    if (kernel == 0 && hole_on(c, 0)) return 2.0 * A.hole_mfma * (double)((B.l + 15) / 16 * 16);
+    if (kernel == 1 && hole_on(c, 1)) return 2.0 * B.hole_mfma * (double)((A.l + 15) / 16 * 16);
     if (kernel == 0) return 2.0 * (double)A.n_a * (double)B.l;
     if (kernel == 1) return 2.0 * (double)B.n_a * (double)A.l;
     const int nmt = (c.P + 15) / 16;

@@ -75,6 +75,23 @@ struct Spin {
     // g_off[row * (4 ntile + 1) + 4 t + g] is the start of that group in the row
     Ent *g_ent = nullptr;
     int32_t *g_off = nullptr;
+    // hole-pair form of the same-spin operator (built on request, n >= 2):
+    // the (n-2)-electron hole strings K of the spin's strings, each with
+    // its entries (string x, occupied pair p<q with K = x - {p, q}, sign);
+    // h_inv lists the entries of each string
+    bool hole_built = false;     // hole_build ran (index on the device or not)
+    bool hole = false;           // index on the device
+    bool hole_auto = false;      // the automatic method takes it (see hole_build)
+    int hmax = 0;                // longest hole-string list
+    int npo = 0;                 // occupied pairs per string, n(n-1)/2
+    int pp = 0;                  // orbital pairs p<q, M(M-1)/2
+    int64_t n_hole = 0, n_hent = 0;
+    double hole_mfma = 0.0;      // sum over K of its padded product block, 16 MT x 4 k-steps
+    int64_t *h_ptr = nullptr;    // [n_hole + 1]
+    uint2 *h_ent = nullptr;      // [n_hent]: .x string, .y pair | sign << 16
+    int32_t *h_inv = nullptr;    // [l][npo] entry positions
+    double *hW = nullptr;        // [pp][pp] pair-pair operator (see hole_sweep.hip)
+    float *hW32 = nullptr;
 };
 
 // The beta sweep runs on C^T: for a block of alpha rows it transposes the
@@ -163,6 +180,11 @@ struct Ctx {
     // beta_block_rows)
     void *work = nullptr;
     size_t work_bytes = 0;
+    // same-spin method (tbsci_set_same_spin) and the hole-pair sweep's
+    // product buffer (allocated on first use)
+    int same_spin = TBSCI_SAME_SPIN_AUTO;
+    void *hole_work = nullptr;
+    size_t hole_work_bytes = 0;
     // per-kernel event timing (measurement only)
     bool timing = false;
     struct TimedCall {
@@ -296,8 +318,19 @@ void launch_sigma(Ctx &c, const void *C, void *S, int precision, hipStream_t st,
 // created on first use, an allocation)
 // fixed-point staging entries deterministic sigma needs for this context
 int64_t det_stage_entries(const Ctx &c);
+// hole-pair sweep (hole_sweep.hip): build a spin's hole-string index and
+// pair operator; whether a spin's same-spin term takes it; its product
+// buffer; Y = A_s X for a spin (X, Y: [l_s][ncols], precision's type)
+void hole_build(Ctx &c, int spin, bool force);
+bool hole_on(const Ctx &c, int spin);
+bool hole_any(const Ctx &c);
+void *hole_workspace(Ctx &c);
+void hole_sweep(Ctx &c, int spin, int64_t ncols, const void *X, void *Y, int precision,
+                void *work, size_t work_bytes, hipStream_t st);
+void free_hole(Spin &s);
 void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
-                     void *work, size_t work_bytes, bool marks);
+                     void *work, size_t work_bytes, bool marks, void *hwork = nullptr,
+                     size_t hbytes = 0);
 double executed_flops(Ctx &c, int kernel, int precision);
 // sigma of n problems in shared launches (one per kernel type, the
 // opposite-spin term one per group of equal tile shape); C[i], S[i] are

@@ -44,6 +44,7 @@ TBSCI_GUESS_SUBSPACE = 2
 TBSCI_STORE_AUTO = 0
 TBSCI_STORE_FULL = 1
 TBSCI_STORE_LEAN = 2
+TBSCI_SAME_SPIN_AUTO, TBSCI_SAME_SPIN_CSR, TBSCI_SAME_SPIN_HOLE = 0, 1, 2
 
 
 class DavidsonOpts(ctypes.Structure):
@@ -112,6 +113,7 @@ def load():
         "tbsci_get_list": (c_int, [P, c_int, c_int, P, P, P]),
         "tbsci_timing_enable": (c_int, [P, c_int]),
         "tbsci_set_deterministic": (c_int, [P, c_int]),
+        "tbsci_set_same_spin": (c_int, [P, c_int]),
         "tbsci_timing_read": (c_int, [P, c_int, c_int, P, P, P, P, P]),
         "tbsci_timing_executed_flops": (c_int, [P, c_int, c_int, P]),
         "tbsci_sigma_batch": (c_int, [P, c_int, P, P, c_int, P]),
@@ -274,6 +276,10 @@ def tbsci_get_list(ctx, spin, kind, l):
 
 
 TBSCI_N_KERNELS = 3
+
+
+def tbsci_set_same_spin(ctx, method):
+    _check(load().tbsci_set_same_spin(ctx, int(method)))
 
 
 def tbsci_set_deterministic(ctx, enable=True):
@@ -507,6 +513,10 @@ class Context:
 
     def _shape(self):
         return (self.n_det,) if getattr(self, "compact", False) else (self.l_alpha, self.l_beta)
+
+    def set_same_spin(self, method):
+        """TBSCI_SAME_SPIN_AUTO, _CSR or _HOLE for the two same-spin terms."""
+        tbsci_set_same_spin(self._ctx, method)
 
     def set_deterministic(self, enable=True):
         """Bitwise-reproducible sigma for this context (alone or batched)."""

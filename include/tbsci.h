@@ -276,7 +276,7 @@ int tbsci_set_deterministic(tbsci_ctx *ctx, int enable);
  * (built by tbsci_create for the spins the automatic method takes, else
  * here) copies the strings and integrals to the host, sorts N(N-1)/2
  * entries per string and holds about 16 B per entry on the device; the
- * hole-pair sweep also allocates a product buffer of up to 2 GiB on first
+ * hole-pair sweep also allocates a product buffer of up to 4 GiB on first
  * use.  A context on the hole-pair sweep builds its sigma alone in batched
  * calls.  tbsci_sigma_noalloc always uses CSR.  tbsci_timing_executed_flops
  * of kernels 0 and 1 reports the MFMA work of the hole-pair sweep when it

@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kHB = 256;               // threads per block, both kernels
 constexpr int kHoleMax = 128;          // longest hole-string list taken
-constexpr size_t kHoleWorkCap = size_t(2) << 30;
+constexpr size_t kHoleWorkCap = size_t(4) << 30;
 
 inline int pair_id(int p, int q) { return q * (q - 1) / 2 + p; }  // p < q
 
@@ -61,15 +61,38 @@ struct HoleMma<float> {
     }
 };
 
+// Barrier for the LDS staging: waits for this wave's LDS operations only
+// (lgkmcnt), not for its global loads in flight or its stores of products,
+// which a full __syncthreads would also drain
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <typename T>
+struct Vec16;  // 16-byte vector of T
+template <>
+struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+
 // Products of one hole string K (block K / nb) over the window columns
 // [cb0, cb0 + cpb) (block K % nb):
 //   Y[e][c] = sum_{e'} W[pair e][pair e'] s_e' X[x_e'][c0 + c]
 // for the entries e, e' of K (e global entry positions, Y row stride ldy).
 // Wave w takes M-tiles w, w + 4, ... (16 entries each) with its A fragments
-// in registers for the whole block; the signed X rows of K are staged in
-// LDS 16 CT columns at a time.  KS bounds the 4-deep k-steps (KS = 16:
-// lists of up to 64 entries, MTW = 1; KS = 32: up to 128, MTW = 2).
-template <typename T, int KS, int MTW, int CT>
+// in registers for the whole block.  The signed X rows of K are staged in
+// LDS 16 CT columns at a time, all 4 KS rows (rows past the list zero), in
+// loads of VL elements (16 bytes when the rows are 16-byte aligned); the
+// loads of the next tile are issued before the MFMAs of the current one
+// and applied (sign, zero) when stored, so nothing waits for them early.
+// The k loop runs all KS steps (A is zero past the list), without branches.
+// KS >= ceil(longest list / 4); MTW = 1 for lists of up to 64 entries
+// (four M-tiles), 2 for up to 128.
+template <typename T, int KS, int MTW, int CT, int VL>
 __global__ __launch_bounds__(kHB) void k_hole_gemm(int64_t nb, int64_t cpb, int64_t nwin,
                                                   int64_t ldx, int64_t c0, int64_t ldy,
                                                   const int64_t *__restrict__ hptr,
@@ -77,22 +100,31 @@ __global__ __launch_bounds__(kHB) void k_hole_gemm(int64_t nb, int64_t cpb, int6
                                                   const T *__restrict__ W, int pp,
                                                   const T *__restrict__ X, T *__restrict__ Y) {
     using M = HoleMma<T>;
-    constexpr int TW = 16 * CT;  // columns per staged tile
-    constexpr int LD = TW + 1;   // padded LDS row
-    __shared__ T xs[4 * KS * LD];
-    __shared__ int64_t xoff[4 * KS];  // X row offset of staged row r, or -1
-    __shared__ int xneg[4 * KS];
+    using TV = typename Vec16<T>::type;
+    constexpr int VEC = 16 / sizeof(T);  // elements per thread and staged row segment
+    constexpr int NL = VEC / VL;         // loads per segment
+    constexpr int TW = 16 * CT;          // columns per staged tile
+    constexpr int LD = TW + VEC;         // padded LDS row (16-byte aligned)
+    constexpr int LPR = TW / VEC;        // threads per staged row
+    constexpr int RPP = kHB / LPR;       // rows per staging pass
+    constexpr int R = 4 * KS;            // staged rows
+    constexpr int NP = (R + RPP - 1) / RPP;
+    static_assert(kHB % LPR == 0 && NP * NL <= 32, "staging layout");
+    typedef T TL __attribute__((ext_vector_type(VL)));
+    __shared__ __align__(16) T xs[R * LD];
+    __shared__ int64_t xoff[R];  // X row offset of staged row r, or -1
+    __shared__ int xneg[R];
     const int64_t K = blockIdx.x / nb;
     const int64_t cb0 = (blockIdx.x - K * nb) * cpb;
     const int64_t cb1 = std::min(nwin, cb0 + cpb);
     const int64_t e0 = hptr[K];
     const int nK = (int)(hptr[K + 1] - e0);
-    const int nks = (nK + 3) >> 2, MT = (nK + 15) >> 4;
+    const int MT = (nK + 15) >> 4;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, cl = lane & 15;
 
-    for (int r = tid; r < 4 * nks; r += kHB) {
+    for (int r = tid; r < R; r += kHB) {
         int64_t o = -1;
         int neg = 0;
         if (r < nK) {
@@ -119,21 +151,43 @@ __global__ __launch_bounds__(kHB) void k_hole_gemm(int64_t nb, int64_t cpb, int6
     }
     __syncthreads();
 
-    for (int64_t cc = cb0; cc < cb1; cc += TW) {
-        // xs[r][c] = s_r X[x_r][c0 + cc + c]; rows past the list and
-        // columns past the window are zero
-        const int rows = 4 * nks;
-        for (int i = tid; i < rows * TW; i += kHB) {
-            const int r = i / TW, c = i - r * TW;
-            const int64_t o = xoff[r];
-            T v = T(0);
-            if (o >= 0 && cc + c < cb1) {
-                v = X[o + cc + c];
-                if (xneg[r]) v = -v;
+    // this thread's staged segments: rows p RPP + sr, columns sc .. sc + VEC
+    const int sr = tid / LPR, sc = (tid - sr * LPR) * VEC;
+    TL buf[NP][NL];
+    uint32_t valid = 0;  // bit p NL + k: segment part k of pass p is inside the list and window
+    auto load = [&](int64_t cc) {
+        valid = 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int r = p * RPP + sr;
+            const int64_t o = r < R ? xoff[r] : -1;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int64_t c = cc + sc + k * VL;
+                const bool ok = o >= 0 && c + VL <= cb1;
+                buf[p][k] = *(const TL *)(X + (ok ? o + c : 0));
+                valid |= (uint32_t)ok << (p * NL + k);
             }
-            xs[r * LD + c] = v;
         }
-        __syncthreads();
+    };
+    load(cb0);
+    for (int64_t cc = cb0; cc < cb1; cc += TW) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int r = p * RPP + sr;
+            if (r < R) {
+                const bool neg = xneg[r] != 0;
+#pragma unroll
+                for (int k = 0; k < NL; ++k) {
+                    TL v = buf[p][k];
+                    if (neg) v = -v;
+                    if (!((valid >> (p * NL + k)) & 1u)) v = TL{};
+                    *(TL *)(xs + r * LD + sc + k * VL) = v;
+                }
+            }
+        }
+        lds_barrier();
+        if (cc + TW < cb1) load(cc + TW);  // in flight during the MFMAs
 #pragma unroll
         for (int w = 0; w < MTW; ++w) {
             const int mt = wave + 4 * w;
@@ -143,12 +197,9 @@ __global__ __launch_bounds__(kHB) void k_hole_gemm(int64_t nb, int64_t cpb, int6
                 for (int ct = 0; ct < CT; ++ct) acc[ct] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
-                    if (ks < nks) {
 #pragma unroll
-                        for (int ct = 0; ct < CT; ++ct)
-                            acc[ct] = M::mma(a[w][ks], xs[(4 * ks + g) * LD + 16 * ct + cl],
-                                             acc[ct]);
-                    }
+                    for (int ct = 0; ct < CT; ++ct)
+                        acc[ct] = M::mma(a[w][ks], xs[(4 * ks + g) * LD + 16 * ct + cl], acc[ct]);
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
                     const int64_t col = cc + 16 * ct + cl;
@@ -160,35 +211,75 @@ __global__ __launch_bounds__(kHB) void k_hole_gemm(int64_t nb, int64_t cpb, int6
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();  // every wave's reads of this tile done before the next staging
     }
 }
 
 // O[x][c0 + c] = sum_t s_t Y[e_t][c] over the npo entries e_t of string x
-// (inv: e | sign << 31), in entry order
+// (inv: e | sign << 31), in entry order.  tpr threads per string (a
+// multiple of 64), VEC columns per thread with 16-byte loads of Y (its rows
+// hold ldy >= nwin columns, ldy a multiple of 64).
 template <typename T>
-__global__ __launch_bounds__(kHB) void k_hole_sum(int64_t ncb, int npo, int64_t nwin, int64_t ldo,
-                                                 int64_t c0, int64_t ldy,
+__global__ __launch_bounds__(kHB) void k_hole_sum(int64_t l, int tpr, int npo, int64_t nwin,
+                                                 int64_t ldo, int64_t c0, int64_t ldy,
                                                  const uint32_t *__restrict__ inv,
                                                  const T *__restrict__ Y, T *__restrict__ O) {
-    const int64_t x = blockIdx.x / ncb;
-    const int64_t col = (blockIdx.x - x * ncb) * kHB + threadIdx.x;
-    if (col >= nwin) return;
+    using TV = typename Vec16<T>::type;
+    constexpr int VEC = 16 / sizeof(T);
+    const int64_t x = (int64_t)blockIdx.x * (kHB / tpr) + threadIdx.x / tpr;
+    if (x >= l) return;
     const uint32_t *iv = inv + x * npo;
-    T acc = T(0);
-    for (int t = 0; t < npo; ++t) {
-        const uint32_t u = iv[t];
-        const T v = Y[(int64_t)(u & 0x7fffffffu) * ldy + col];
-        acc += (u >> 31) ? -v : v;
+    T *o = O + x * ldo + c0;
+    for (int64_t c = (int64_t)(threadIdx.x % tpr) * VEC; c < nwin; c += (int64_t)tpr * VEC) {
+        TV acc = {};
+#pragma unroll 4
+        for (int t = 0; t < npo; ++t) {
+            const uint32_t u = iv[t];
+            const TV v = *(const TV *)(Y + (int64_t)(u & 0x7fffffffu) * ldy + c);
+            acc += (u >> 31) ? -v : v;
+        }
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            if (c + k < nwin) o[c + k] = acc[k];
     }
-    O[x * ldo + c0 + col] = acc;
 }
 
-template <typename T, int KS, int MTW, int CT>
+template <typename T, int KS, int MTW, int CT, int VL>
+void launch_gemm_t(const Spin &s, int64_t nb, int64_t cpb, int64_t nwin, int64_t ldx, int64_t c0,
+                   int64_t ldy, const T *W, const T *X, T *Y, hipStream_t st) {
+    k_hole_gemm<T, KS, MTW, CT, VL><<<(unsigned)(s.n_hole * nb), kHB, 0, st>>>(
+        nb, cpb, nwin, ldx, c0, ldy, s.h_ptr, s.h_ent, W, s.pp, X, Y);
+}
+
+// k-step depth: the smallest instance that holds the longest list
+template <typename T, int VL>
+void launch_gemm_v(const Spin &s, int64_t nb, int64_t cpb, int64_t nwin, int64_t ldx, int64_t c0,
+                   int64_t ldy, const T *W, const T *X, T *Y, hipStream_t st) {
+    const int ks = (s.hmax + 3) / 4;
+    if (ks <= 8)
+        launch_gemm_t<T, 8, 1, 4, VL>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
+    else if (ks <= 12)
+        launch_gemm_t<T, 12, 1, 4, VL>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
+    else if (ks <= 14)
+        launch_gemm_t<T, 14, 1, 4, VL>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
+    else if (ks <= 16)
+        launch_gemm_t<T, 16, 1, 4, VL>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
+    else if (ks <= 24)
+        launch_gemm_t<T, 24, 2, 2, VL>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
+    else
+        launch_gemm_t<T, 32, 2, 2, VL>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
+}
+
+// 16-byte loads when every staged segment is 16-byte aligned (X aligned,
+// its rows a whole number of 16-byte units long), else element loads
+template <typename T>
 void launch_gemm(const Spin &s, int64_t nb, int64_t cpb, int64_t nwin, int64_t ldx, int64_t c0,
                  int64_t ldy, const T *W, const T *X, T *Y, hipStream_t st) {
-    k_hole_gemm<T, KS, MTW, CT><<<(unsigned)(s.n_hole * nb), kHB, 0, st>>>(
-        nb, cpb, nwin, ldx, c0, ldy, s.h_ptr, s.h_ent, W, s.pp, X, Y);
+    constexpr int VEC = 16 / sizeof(T);
+    if (ldx % VEC == 0 && (uintptr_t)X % 16 == 0)
+        launch_gemm_v<T, VEC>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
+    else
+        launch_gemm_v<T, 1>(s, nb, cpb, nwin, ldx, c0, ldy, W, X, Y, st);
 }
 
 template <typename T>
@@ -202,18 +293,20 @@ void hole_sweep_t(const Spin &s, int64_t ncols, const T *X, T *Y, void *work, si
     T *Yb = (T *)work;
     const T *W = sizeof(T) == 8 ? (const T *)(const void *)s.hW : (const T *)(const void *)s.hW32;
     const uint32_t *inv = (const uint32_t *)s.h_inv;
+    constexpr int VEC = 16 / sizeof(T);
     for (int64_t c0 = 0; c0 < ncols; c0 += wn) {
         const int64_t nwin = std::min(wn, ncols - c0);
-        const int64_t cpb = 256;
+        // blocks of up to 512 columns: enough of them to fill the chip
+        const int64_t cpb = std::min<int64_t>(512, (nwin + 63) / 64 * 64);
         const int64_t nb = (nwin + cpb - 1) / cpb;
-        if (s.hmax <= 64)
-            launch_gemm<T, 16, 1, 4>(s, nb, cpb, nwin, ncols, c0, wn, W, X, Yb, st);
-        else
-            launch_gemm<T, 32, 2, 2>(s, nb, cpb, nwin, ncols, c0, wn, W, X, Yb, st);
+        launch_gemm<T>(s, nb, cpb, nwin, ncols, c0, wn, W, X, Yb, st);
         TB_HIP(hipGetLastError());
-        const int64_t ncb = (nwin + kHB - 1) / kHB;
-        k_hole_sum<T><<<(unsigned)(s.l * ncb), kHB, 0, st>>>(ncb, s.npo, nwin, ncols, c0, wn, inv,
-                                                             Yb, Y);
+        // threads per string: 64, 128 or 256, covering the window's vectors
+        int tpr = 64;
+        while (tpr < kHB && (int64_t)tpr * VEC < nwin) tpr *= 2;
+        const int64_t rpb = kHB / tpr;
+        k_hole_sum<T><<<(unsigned)((s.l + rpb - 1) / rpb), kHB, 0, st>>>(
+            s.l, tpr, s.npo, nwin, ncols, c0, wn, inv, Yb, Y);
         TB_HIP(hipGetLastError());
     }
 }
@@ -370,7 +463,7 @@ bool hole_any(const Ctx &c) { return hole_on(c, 0) || hole_on(c, 1); }
 
 // product buffer: the entries of the spins that take the hole-pair sweep
 // times the widest window their sweeps use (alpha: l_beta columns; beta:
-// the rows of a beta-sweep block), capped at 2 GiB
+// the rows of a beta-sweep block), capped at 4 GiB
 void *hole_workspace(Ctx &c) {
     size_t need = 0;
     const int64_t la = c.sp[0].l, lb = c.sp[1].l;

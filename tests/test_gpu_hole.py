@@ -164,3 +164,22 @@ def test_same_spin_method_errors(env):
     ctx.set_same_spin(T.TBSCI_SAME_SPIN_AUTO)
     assert T.tbsci_timing_executed_flops(ctx.handle, 0) == csr
     ctx.close()
+
+
+def test_hole_with_reproducible_mode(env):
+    """A context on the hole-pair sweeps (the complete M = 16 space, taken
+    by the automatic method) in the reproducible mode: two whole sigma
+    builds bitwise equal, and equal to the default mode's to 1e-12."""
+    T, O, torch = env
+    p = W.make_problem("fci_m16", 16, 8, None, 1006)
+    ctx = T.Context.from_problem(p)
+    Cg = torch.from_numpy(np.random.default_rng(12).normal(size=(ctx.l_alpha,
+                                                                  ctx.l_beta))).cuda()
+    ref = ctx.sigma(Cg).cpu().numpy()
+    ctx.set_deterministic(True)
+    a = ctx.sigma(Cg).cpu().numpy()
+    b = ctx.sigma(Cg).cpu().numpy()
+    assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    e, m = _rel(a, ref)
+    assert e <= 1e-12 and m <= 1e-12, (e, m)
+    ctx.close()

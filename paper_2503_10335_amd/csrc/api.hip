@@ -73,7 +73,7 @@ void free_spin(Spin &s) {
     free_hole(s);
     void *ptrs[] = {s.str,   s.keys,  s.pos,     s.s_ptr, s.s_ent, s.d_ptr, s.d_ent,
                     s.a_ptr, s.a_col, s.a_val,   s.a_val32, s.dsame, s.jocc,  s.g_ent,
-                    s.g_off, s.b_off, s.b_col,   s.b_val, s.b_val32};
+                    s.g_off, s.b_off, s.b_col,   s.b_val, s.b_val32, s.ks_rows};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     s = Spin{};
@@ -267,6 +267,7 @@ Ctx *create_ctx(int M, int n_alpha, int n_beta, const double *h, const double *e
                 build_spin(*c, c->sp[0], alpha, st);
                 build_spin(*c, c->sp[1], beta, st);
                 TB_HIP(hipStreamSynchronize(st));
+                build_ks_classes(c->sp[0]);
                 // hole-pair index of the spins the automatic method gives it to
                 hole_build(*c, 0, false);
                 hole_build(*c, 1, false);

@@ -560,4 +560,30 @@ void launch_full_diag(const Ctx &c, double *out, hipStream_t st) {
 }
 
 
+void build_ks_classes(Spin &s) {
+    if (s.ks_rows) TB_HIP(hipFree(s.ks_rows));
+    s.ks_rows = nullptr;
+    std::vector<int64_t> ptr((size_t)s.l + 1);
+    TB_HIP(hipMemcpy(ptr.data(), s.s_ptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    static const int kcls[5] = {8, 16, 24, 28, 32};
+    std::vector<int32_t> cls[5];
+    for (int64_t i = 0; i < s.l; ++i) {
+        const int64_t ks = (ptr[(size_t)i + 1] - ptr[(size_t)i] + 3) / 4;
+        int k = 0;
+        while (k < 4 && ks > kcls[k]) ++k;
+        cls[k].push_back((int32_t)i);
+    }
+    std::vector<int32_t> rows;
+    rows.reserve((size_t)s.l);
+    s.ks_off[0] = 0;
+    for (int k = 0; k < 5; ++k) {
+        rows.insert(rows.end(), cls[k].begin(), cls[k].end());
+        s.ks_off[k + 1] = (int64_t)rows.size();
+    }
+    TB_HIP(hipMalloc((void **)&s.ks_rows, std::max<size_t>(rows.size(), 1) * sizeof(int32_t)));
+    if (!rows.empty())
+        TB_HIP(hipMemcpy(s.ks_rows, rows.data(), rows.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+}
+
 }  // namespace tbsci

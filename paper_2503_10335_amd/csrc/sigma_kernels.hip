@@ -705,23 +705,26 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
         if (sl >= nslab) break;
         const int64_t col = (int64_t)sl * 16 + cl;
         const bool cin = col < lb;
+        // C fragments of all KS k-steps, without branches: every load goes to
+        // a valid address (element 0 for steps past the list or columns past
+        // lb) and is replaced by zero when used, so no wait is forced early
         T b[KS];
         {
             int32_t J[KS];
 #pragma unroll
             for (int q = 0; q < KS / 4; ++q) {
-                int4 j4 = make_int4(-1, -1, -1, -1);
-                if (4 * q < nks) j4 = *(const int4 *)(ajg + 4 * q);
-                J[4 * q] = j4.x;
-                J[4 * q + 1] = j4.y;
-                J[4 * q + 2] = j4.z;
-                J[4 * q + 3] = j4.w;
+                const int4 j4 = *(const int4 *)(ajg + std::min(4 * q, std::max(nk4 - 4, 0)));
+                const int jj[4] = {j4.x, j4.y, j4.z, j4.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) J[4 * q + u] = 4 * q + u < nk4 ? jj[u] : -1;
             }
 #pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                b[ks] = C[(J[ks] >= 0 && cin) ? (int64_t)J[ks] * lb + col : 0];
+#pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                T v = T(0);
-                if (J[ks] >= 0 && cin) v = C[(int64_t)J[ks] * lb + col];
-                b[ks] = ((sgn >> ks) & 1u) ? -v : v;
+                const T x = (J[ks] >= 0 && cin) ? b[ks] : T(0);
+                b[ks] = ((sgn >> ks) & 1u) ? -x : x;
             }
         }
         const int32_t *off = sb_off + (cin ? col : 0) * (ng + 1) + g;
@@ -744,33 +747,32 @@ __device__ __forceinline__ void ab_slabg_row(const int64_t I, int64_t lb, int P,
                 n1 = off[4 * (m + 1) + 1];
             }
             // this lane's column of V for tile m (row 0 stands in for pairs
-            // past P; their fragments are zeroed)
+            // past P: those accumulator rows are never scattered)
             const int pr = 16 * m + r16;
-            const bool pin = pr < P;
-            const T *Vm = V + (pin ? pr : 0);
+            const T *Vm = V + (pr < P ? pr : 0);
             // A fragments of k-step group q: V[pq_k P + pr] for the group's
-            // four k-steps (padding steps read row 0; their C fragments are 0)
+            // four k-steps; steps past the list read offset 0 (their C
+            // fragments are zero).  All KS steps run, without branches.
             auto ldg = [&](int q, T *a) {
-                const int4 o4 = *(const int4 *)(apg + 4 * q);
-                a[0] = pin ? Vm[o4.x & 0xffff] : T(0);
-                a[1] = pin ? Vm[o4.y & 0xffff] : T(0);
-                a[2] = pin ? Vm[o4.z & 0xffff] : T(0);
-                a[3] = pin ? Vm[o4.w & 0xffff] : T(0);
+                int4 o4 = *(const int4 *)(apg + std::min(4 * q, std::max(nk4 - 4, 0)));
+                if (4 * q >= nk4) o4 = make_int4(0, 0, 0, 0);
+                a[0] = Vm[o4.x & 0xffff];
+                a[1] = Vm[o4.y & 0xffff];
+                a[2] = Vm[o4.z & 0xffff];
+                a[3] = Vm[o4.w & 0xffff];
             };
             typename M::acc_t acc = typename M::acc_t{0, 0, 0, 0};
-            T an[G] = {};
-            if (nks > 0) ldg(0, an);
+            T an[G];
+            ldg(0, an);
 #pragma unroll
-            for (int q = 0; q < KS / G; ++q)
-                if (G * q < nks) {
-                    T a[G];
+            for (int q = 0; q < KS / G; ++q) {
+                T a[G];
 #pragma unroll
-                    for (int u = 0; u < G; ++u) a[u] = an[u];
-                    if (G * (q + 1) < nks) ldg(q + 1, an);
+                for (int u = 0; u < G; ++u) a[u] = an[u];
+                if (q + 1 < KS / G) ldg(q + 1, an);
 #pragma unroll
-                    for (int u = 0; u < G; ++u)
-                        if (G * q + u < nks) acc = M::mma(a[u], b[G * q + u], acc);
-                }
+                for (int u = 0; u < G; ++u) acc = M::mma(a[u], b[G * q + u], acc);
+            }
             auto put = [&](const Ent &e) {
                 T v = pick4(acc, (int)(((e.o >> 16) & 15) >> 2));
                 if ((e.o >> 12) & 1u) v = -v;
@@ -818,9 +820,10 @@ __global__ __launch_bounds__(kSlabBlock) void k_ab_slabg(int64_t lb, int P, int 
                                                         const T *__restrict__ C,
                                                         T *__restrict__ S,
                                                         const double *__restrict__ det,
-                                                        unsigned long long *__restrict__ stage) {
-    ab_slabg_row<T, KS, ROW>(blockIdx.x, lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp, sb_off,
-                             V, C, S, det, stage);
+                                                        unsigned long long *__restrict__ stage,
+                                                        const int32_t *__restrict__ rows) {
+    ab_slabg_row<T, KS, ROW>(rows[blockIdx.x], lb, P, nmt, L, sa_ptr, sa_ent, sb_ptr, sb_grp,
+                             sb_off, V, C, S, det, stage);
 }
 
 // one problem of a grouped slab launch: blocks [blk0, blk0 + l_alpha)
@@ -951,9 +954,29 @@ bool slabg_fits(const Ctx &c) {
 }
 
 template <typename T, int KS>
-void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
+void launch_ab_slabg_class(Ctx &c, int row, const SlabgLds &L, const int32_t *rows,
+                           int64_t n, const T *C, T *S, hipStream_t st) {
     const Spin &A = c.sp[0], &B = c.sp[1];
     const int P = c.P, nmt = (P + 15) / 16;
+    auto f = row == kRowF64      ? k_ab_slabg<T, KS, kRowF64>
+             : row == kRowT      ? k_ab_slabg<T, KS, kRowT>
+             : row == kRowSplitT ? k_ab_slabg<T, KS, kRowSplitT>
+                                 : k_ab_slabg<T, KS, kRowSplit>;
+    if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
+    f<<<(unsigned)n, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
+                                                B.g_ent, B.g_off, Vals<T>::V(c), C, S,
+                                                c.det ? c.det_buf + 1 : nullptr,
+                                                c.det ? c.det_stage : nullptr, rows);
+    TB_HIP(hipGetLastError());
+}
+
+// The global-fragment kernel runs a fixed number of k-steps per row (no
+// branches in its MFMA loop), so the alpha rows go in classes by their own
+// k-step count (8, 16, 24, 28, 32; lists built at create time), one launch
+// per class, all with the LDS layout of the longest list.
+template <typename T>
+void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
+    const Spin &A = c.sp[0], &B = c.sp[1];
     const int ks = std::max((A.max_s + 3) / 4, 1);
     // an FP64 row (split when the whole row does not fit); FP32 sigma with
     // a long row keeps a whole FP32 row instead when that fits
@@ -978,16 +1001,14 @@ void launch_ab_slabg(Ctx &c, const T *C, T *S, hipStream_t st) {
     if (c.det && row == kRowSplit &&
         (!c.det_stage || c.det_stage_n < A.l * (B.l - L.nrow)))
         throw Error(TBSCI_E_STATE, "deterministic sigma: the fixed-point staging area is missing");
-    auto f = row == kRowF64      ? k_ab_slabg<T, KS, kRowF64>
-             : row == kRowT      ? k_ab_slabg<T, KS, kRowT>
-             : row == kRowSplitT ? k_ab_slabg<T, KS, kRowSplitT>
-                                 : k_ab_slabg<T, KS, kRowSplit>;
-    if (L.total > 64 * 1024) allow_lds(c, (const void *)f, L.total);
-    f<<<(unsigned)A.l, kSlabBlock, L.total, st>>>(B.l, P, nmt, L, A.s_ptr, A.s_ent, B.s_ptr,
-                                                  B.g_ent, B.g_off, Vals<T>::V(c), C, S,
-                                                  c.det ? c.det_buf + 1 : nullptr,
-                                                  c.det ? c.det_stage : nullptr);
-    TB_HIP(hipGetLastError());
+    if (!A.ks_rows) throw Error(TBSCI_E_STATE, "alpha row classes missing");
+    const int64_t *o = A.ks_off;
+    const int32_t *r = A.ks_rows;
+    if (o[1] > o[0]) launch_ab_slabg_class<T, 8>(c, row, L, r + o[0], o[1] - o[0], C, S, st);
+    if (o[2] > o[1]) launch_ab_slabg_class<T, 16>(c, row, L, r + o[1], o[2] - o[1], C, S, st);
+    if (o[3] > o[2]) launch_ab_slabg_class<T, 24>(c, row, L, r + o[2], o[3] - o[2], C, S, st);
+    if (o[4] > o[3]) launch_ab_slabg_class<T, 28>(c, row, L, r + o[3], o[4] - o[3], C, S, st);
+    if (o[5] > o[4]) launch_ab_slabg_class<T, 32>(c, row, L, r + o[4], o[5] - o[4], C, S, st);
 }
 
 // KS instance of the slab kernel for a context (0: it does not apply)
@@ -1024,17 +1045,7 @@ bool launch_ab(Ctx &c, const T *C, T *S, hipStream_t st) {
         default: break;
     }
     if (!slabg_fits(c)) return false;
-    const int ks = std::max((c.sp[0].max_s + 3) / 4, 1);
-    if (ks <= 8)
-        launch_ab_slabg<T, 8>(c, C, S, st);
-    else if (ks <= 16)
-        launch_ab_slabg<T, 16>(c, C, S, st);
-    else if (ks <= 24)
-        launch_ab_slabg<T, 24>(c, C, S, st);
-    else if (ks <= 28)
-        launch_ab_slabg<T, 28>(c, C, S, st);
-    else
-        launch_ab_slabg<T, 32>(c, C, S, st);
+    launch_ab_slabg<T>(c, C, S, st);
     return true;
 }
 
@@ -1370,13 +1381,19 @@ double executed_flops(Ctx &c, int kernel, int precision) {
     const int nmt = (c.P + 15) / 16;
     const bool slab = slab_ks(c, precision == TBSCI_FP32 ? sizeof(float) : sizeof(double)) > 0;
     if (!slab && !slabg_fits(c)) return 2.0 * (double)A.n_s * (double)B.n_s;
+    const double cols = (double)((B.l + 15) / 16) * 16;
+    double kp = 0.0;
+    if (!slab) {
+        // global-fragment kernel: every row of a class runs the class's k-steps
+        static const int kcls[5] = {8, 16, 24, 28, 32};
+        for (int k = 0; k < 5; ++k) kp += 4.0 * kcls[k] * (double)(A.ks_off[k + 1] - A.ks_off[k]);
+        return 2.0 * kp * (16.0 * nmt) * cols;
+    }
     std::vector<int64_t> ptr((size_t)A.l + 1);
     TB_HIP(hipMemcpy(ptr.data(), A.s_ptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-    const int64_t pad = slab && precision == TBSCI_FP32 ? 16 : 4;
-    double kp = 0.0;
+    const int64_t pad = precision == TBSCI_FP32 ? 16 : 4;
     for (int64_t i = 0; i < A.l; ++i)
         kp += (double)(pad * ((ptr[i + 1] - ptr[i] + pad - 1) / pad));
-    const double cols = (double)((B.l + 15) / 16) * 16;
     return 2.0 * kp * (16.0 * nmt) * cols;
 }
 

@@ -75,6 +75,11 @@ struct Spin {
     // g_off[row * (4 ntile + 1) + 4 t + g] is the start of that group in the row
     Ent *g_ent = nullptr;
     int32_t *g_off = nullptr;
+    // the strings in classes by the k-steps of their singles lists,
+    // ceil(len / 4) <= 8, 16, 24, 28, 32: class k holds ks_rows[ks_off[k] ..
+    // ks_off[k+1]) (the global-fragment opposite-spin kernel's launches)
+    int32_t *ks_rows = nullptr;
+    int64_t ks_off[6] = {0, 0, 0, 0, 0, 0};
     // hole-pair form of the same-spin operator (built on request, n >= 2):
     // the (n-2)-electron hole strings K of the spin's strings, each with
     // its entries (string x, occupied pair p<q with K = x - {p, q}, sign);
@@ -328,6 +333,8 @@ void *hole_workspace(Ctx &c);
 void hole_sweep(Ctx &c, int spin, int64_t ncols, const void *X, void *Y, int precision,
                 void *work, size_t work_bytes, hipStream_t st);
 void free_hole(Spin &s);
+// build a spin's k-step classes (ks_rows, ks_off) from its singles lists
+void build_ks_classes(Spin &s);
 void launch_sigma_ws(Ctx &c, const void *C, void *S, int precision, hipStream_t st, int terms,
                      void *work, size_t work_bytes, bool marks, void *hwork = nullptr,
                      size_t hbytes = 0);

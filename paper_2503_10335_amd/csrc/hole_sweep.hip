@@ -349,6 +349,10 @@ void hole_build(Ctx &c, int spin, bool force) {
     const int n = s.n, M = c.M;
     const int64_t l = s.l;
     if (n < 2 || l == 0) return;
+    // the automatic method only takes spaces too large for grouped launches:
+    // for the others nothing is built unless asked for
+    const bool large = beta_block_rows(c.sp[0].l, c.sp[1].l, kWorkCap) < c.sp[0].l;
+    if (!force && !large) return;
     std::vector<uint64_t> str((size_t)l);
     TB_HIP(hipMemcpy(str.data(), s.str, (size_t)l * 8, hipMemcpyDeviceToHost));
     const size_t M2 = (size_t)M * M;
@@ -399,7 +403,6 @@ void hole_build(Ctx &c, int spin, bool force) {
     ptr.push_back((int64_t)ent.size());
     if (hmax > kHoleMax || ent.size() >= (size_t(1) << 31)) return;  // keeps the CSR sweep
     const bool dense = ent.size() >= (size_t)TBSCI_HOLE_AUTO_MIN * (ptr.size() - 1);
-    const bool large = beta_block_rows(c.sp[0].l, c.sp[1].l, kWorkCap) < c.sp[0].l;
     s.hole_auto = dense && large;
     if (!force && !s.hole_auto) return;
 

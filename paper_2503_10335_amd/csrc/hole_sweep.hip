@@ -100,7 +100,6 @@ __global__ __launch_bounds__(kHB) void k_hole_gemm(int64_t nb, int64_t cpb, int6
                                                   const T *__restrict__ W, int pp,
                                                   const T *__restrict__ X, T *__restrict__ Y) {
     using M = HoleMma<T>;
-    using TV = typename Vec16<T>::type;
     constexpr int VEC = 16 / sizeof(T);  // elements per thread and staged row segment
     constexpr int NL = VEC / VL;         // loads per segment
     constexpr int TW = 16 * CT;          // columns per staged tile

@@ -624,8 +624,8 @@ def main():
         args.davidson_workload = ""
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (one process holds the whole CI "
-              "vector); --gpus must be 1.", file=sys.stderr, flush=True)
+        print("bench.py: the library runs on one GPU (one process holds the whole CI "
+              "vector and sigma); --gpus must be 1.", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import torch

@@ -205,7 +205,8 @@ __global__ __launch_bounds__(kHB) void k_hole_gemm(int64_t nb, int64_t cpb, int6
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int e = 16 * mt + M::row(lane, r);
-                        if (e < nK && col < cb1) Y[(e0 + e) * ldy + col] = acc[ct][r];
+                        if (e < nK && col < cb1)
+                            __builtin_nontemporal_store(acc[ct][r], &Y[(e0 + e) * ldy + col]);
                     }
                 }
             }
@@ -234,7 +235,8 @@ __global__ __launch_bounds__(kHB) void k_hole_sum(int64_t l, int tpr, int npo, i
 #pragma unroll 4
         for (int t = 0; t < npo; ++t) {
             const uint32_t u = iv[t];
-            const TV v = *(const TV *)(Y + (int64_t)(u & 0x7fffffffu) * ldy + c);
+            const TV v =
+                __builtin_nontemporal_load((const TV *)(Y + (int64_t)(u & 0x7fffffffu) * ldy + c));
             acc += (u >> 31) ? -v : v;
         }
 #pragma unroll

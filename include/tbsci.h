@@ -235,16 +235,20 @@ int tbsci_sigma_terms(tbsci_ctx *ctx, const void *C_dev, void *sigma_dev, int pr
  * in 64-bit fixed point -- a power-of-two scale, taken per call from
  * max|C|, max|(pq|rs)| and the longest single-excitation lists so that no
  * partial sum can overflow -- so the order of its atomic adds no longer
- * matters; the same-spin sweeps run in one fixed order.  Rounding: each
- * opposite-spin contribution is rounded to 2^-62 of that bound, below the
- * FP64 parity tolerance for any C.  Opposite-spin rows longer than LDS
+ * matters.  The same-spin terms have no atomics; a space small enough to
+ * share grouped launches sweeps in the grouped launches' order (alone =
+ * batched), larger ones keep their panel, chunked or hole-pair sweeps.
+ * Rounding: each opposite-spin contribution is rounded to a unit of
+ * 2^-62 of that bound (K_alpha K_beta max|(pq|rs)| max|C|, K = longest
+ * single-excitation list), about 1e-15 relative to sigma in the tested
+ * spaces.  Opposite-spin rows longer than LDS
  * holds (l_beta above about 20,000 strings) keep their remainder in a
  * device staging area of l_alpha x (l_beta - that length) 8-byte entries,
  * allocated here on enable (11 GB at l_alpha = l_beta = 48,620) and left
  * zeroed by every sigma; FP32 sigma then also keeps an 8-byte row.  The
  * call allocates 16 bytes plus that area (TBSCI_E_DEVICE when it does not
  * fit); the memory is held until tbsci_destroy.  enable == 0 returns to
- * the default (FP64 atomics, chunked and panel sweeps).
+ * the default (FP64 atomics in the opposite-spin rows).
  */
 int tbsci_set_deterministic(tbsci_ctx *ctx, int enable);
 
